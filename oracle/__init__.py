@@ -1,0 +1,201 @@
+"""ctypes front end of the CPU FP64 oracle (oracle/liboracle.so).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this module; the product path never does.  The
+C sources beside it are independent of the HIP path and share nothing with it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+STATUS = {0: "OK", 1: "MAXSTEPS", 2: "ERRTEST", 3: "CONV", 4: "HMIN", 5: "NONFINITE"}
+STAT_FIELDS = ("nst", "nfe", "nje", "nlu", "nni", "netf", "ncf")
+
+
+class _Net(C.Structure):
+    _fields_ = [("ns", C.c_int), ("thermal", C.c_int), ("nr", C.c_int),
+                ("reactant", C.POINTER(C.c_int32)), ("product", C.POINTER(C.c_int32)),
+                ("lnA", C.POINTER(C.c_double)), ("n_exp", C.POINTER(C.c_double)),
+                ("E", C.POINTER(C.c_double)), ("q", C.POINTER(C.c_double))]
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32)) if a is not None else None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        _lib = C.CDLL(_LIB_PATH)
+        d, i, p = C.c_double, C.c_int, C.c_void_p
+        _lib.orc_burn.restype = i
+        _lib.orc_burn.argtypes = [p, p, C.c_int64, p, d, d, d, i, p, p, i]
+        _lib.orc_burn_zone.restype = i
+        _lib.orc_burn_zone.argtypes = [p, p, p, d, d, d, i, p]
+        _lib.orc_rhs.argtypes = [p, p, p, p]
+        _lib.orc_rhs_cplx.argtypes = [p, p, p, p]
+        _lib.orc_jac.argtypes = [p, p, p, p]
+        _lib.orc_rates.argtypes = [p, p, p, p, p]
+        _lib.orc_lu.restype = i
+        _lib.orc_lu.argtypes = [i, p, p]
+        _lib.orc_lu_solve.argtypes = [i, p, p, p]
+        _lib.orc_lcoef.argtypes = [i, p]
+        _lib.orc_stirling.argtypes = [i, p]
+        _lib.orc_order_raise.argtypes = [i, i, p, p]
+        _lib.orc_order_lower.argtypes = [i, i, p]
+        _lib.orc_fixed_steps.restype = i
+        _lib.orc_fixed_steps.argtypes = [p, p, i, d, i, p, p, p]
+        _lib.orc_radau.restype = i
+        _lib.orc_radau.argtypes = [p, p, p, d, C.c_int64, d]
+        _lib.orc_check_net.restype = i
+        _lib.orc_check_net.argtypes = [p]
+    return _lib
+
+
+class Net:
+    """Holds the numpy arrays of a network dict alive for the C struct."""
+
+    def __init__(self, net):
+        self.ns = int(net["n_species"])
+        self.thermal = int(net["thermal"])
+        self.reactant = np.ascontiguousarray(net["reactant"], dtype=np.int32)
+        self.product = np.ascontiguousarray(net["product"], dtype=np.int32)
+        self.lnA = np.ascontiguousarray(net["lnA"], dtype=np.float64)
+        self.n_exp = np.ascontiguousarray(net["n_exp"], dtype=np.float64)
+        self.E = np.ascontiguousarray(net["E"], dtype=np.float64)
+        self.q = np.ascontiguousarray(net["q"], dtype=np.float64)
+        self.nr = int(self.lnA.shape[0])
+        self.nv = self.ns + self.thermal
+        self.s = _Net(self.ns, self.thermal, self.nr, _ip(self.reactant), _ip(self.product),
+                      _dp(self.lnA), _dp(self.n_exp), _dp(self.E), _dp(self.q))
+        if lib().orc_check_net(C.byref(self.s)):
+            raise ValueError("invalid network")
+
+    @property
+    def ref(self):
+        return C.byref(self.s)
+
+
+def _as_net(net):
+    return net if isinstance(net, Net) else Net(net)
+
+
+def burn(net, state, dt, rtol, atol, scale=None, max_steps=100000, nthreads=None):
+    """Burn a copy of state [zones][ns+1]; returns (state, status[zones], stats[zones,7])."""
+    n = _as_net(net)
+    st = np.array(state, dtype=np.float64, copy=True, order="C")
+    zones = st.shape[0]
+    if st.ndim != 2 or st.shape[1] != n.ns + 1:
+        raise ValueError("state must be [zones][ns+1]")
+    sc = None if scale is None else np.ascontiguousarray(scale, dtype=np.float64)
+    if sc is not None and sc.shape != (zones, n.nr):
+        raise ValueError("scale must be [zones][R]")
+    status = np.zeros(zones, dtype=np.int32)
+    stats = np.zeros((zones, 7), dtype=np.int32)
+    if nthreads is None:
+        nthreads = os.cpu_count() or 1
+    lib().orc_burn(n.ref, _dp(st), zones, _dp(sc), dt, rtol, atol, int(max_steps), _ip(status),
+                   _ip(stats), int(nthreads))
+    return st, status, stats
+
+
+def rhs(net, y, scale=None):
+    n = _as_net(net)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    f = np.zeros(n.nv)
+    sc = None if scale is None else np.ascontiguousarray(scale, dtype=np.float64)
+    lib().orc_rhs(n.ref, _dp(sc), _dp(y), _dp(f))
+    return f
+
+
+def rhs_complex(net, y, scale=None):
+    n = _as_net(net)
+    y = np.ascontiguousarray(y, dtype=np.complex128)
+    f = np.zeros(n.nv, dtype=np.complex128)
+    sc = None if scale is None else np.ascontiguousarray(scale, dtype=np.float64)
+    lib().orc_rhs_cplx(n.ref, _dp(sc), y.ctypes.data_as(C.c_void_p), f.ctypes.data_as(C.c_void_p))
+    return f
+
+
+def jac(net, y, scale=None):
+    n = _as_net(net)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    J = np.zeros((n.nv, n.nv))
+    sc = None if scale is None else np.ascontiguousarray(scale, dtype=np.float64)
+    lib().orc_jac(n.ref, _dp(sc), _dp(y), _dp(J))
+    return J
+
+
+def lu(A):
+    A = np.array(A, dtype=np.float64, copy=True, order="C")
+    n = A.shape[0]
+    piv = np.zeros(n, dtype=np.int32)
+    info = lib().orc_lu(n, _dp(A), _ip(piv))
+    return A, piv, info
+
+
+def lu_solve(LU, piv, b):
+    b = np.array(b, dtype=np.float64, copy=True)
+    lib().orc_lu_solve(LU.shape[0], _dp(np.ascontiguousarray(LU)), _ip(piv), _dp(b))
+    return b
+
+
+def lcoef(q):
+    l = np.zeros(q + 1)
+    lib().orc_lcoef(q, _dp(l))
+    return l
+
+
+def stirling(n):
+    c = np.zeros(n + 1)
+    lib().orc_stirling(n, _dp(c))
+    return c
+
+
+def order_raise(Z, q, dy):
+    """Z: [q+2][nv] (row q+1 is overwritten)."""
+    Z = np.array(Z, dtype=np.float64, copy=True, order="C")
+    lib().orc_order_raise(Z.shape[1], q, _dp(Z), _dp(np.ascontiguousarray(dy, dtype=np.float64)))
+    return Z
+
+
+def order_lower(Z, q):
+    Z = np.array(Z, dtype=np.float64, copy=True, order="C")
+    lib().orc_order_lower(Z.shape[1], q, _dp(Z))
+    return Z
+
+
+def fixed_steps(net, Z, q, h, nsteps, scale=None, with_errors=False):
+    n = _as_net(net)
+    Z = np.array(Z, dtype=np.float64, copy=True, order="C")
+    ys = np.zeros((nsteps, n.nv))
+    errs = np.zeros(nsteps)
+    sc = None if scale is None else np.ascontiguousarray(scale, dtype=np.float64)
+    rc = lib().orc_fixed_steps(n.ref, _dp(sc), q, h, nsteps, _dp(Z), _dp(ys), _dp(errs))
+    if rc:
+        raise RuntimeError(f"Newton failed at step {rc}")
+    return (ys, Z, errs) if with_errors else (ys, Z)
+
+
+def radau(net, y0, dt, nsteps, h0=0.0, scale=None):
+    n = _as_net(net)
+    y = np.array(y0, dtype=np.float64, copy=True)[: n.nv].copy()
+    sc = None if scale is None else np.ascontiguousarray(scale, dtype=np.float64)
+    rc = lib().orc_radau(n.ref, _dp(sc), _dp(y), dt, int(nsteps), h0)
+    if rc:
+        raise RuntimeError(f"Radau Newton failed at step {-rc}")
+    return y

@@ -1,0 +1,353 @@
+/*
+ * Oracle BDF integrator (test infrastructure only; see oracle.h).
+ *
+ * The paper names VODE (Brown, Byrne & Hindmarsh 1989) as its stiff
+ * integrator and states none of its rules.  This file is the reading used by
+ * the whole project, written from the published theory of Nordsieck-form BDF
+ * methods (fixed leading coefficient, interpolatory rescaling):
+ *
+ *  Norm     |v| = sqrt(mean_i (v_i / w_i)^2), w_i = atol + rtol |y_i| taken from
+ *           the last accepted y and held for the whole step attempt.
+ *  History  Z_j = h^j y^(j) / j!, j = 0..q (q <= 5).  Prediction multiplies Z
+ *           by the Pascal matrix.  l(q) = coefficients of prod_{i<=q}(1 + x/i),
+ *           divided by the harmonic number H_q so that l_1 = 1; gamma = h l_0.
+ *  Start    The Hairer-Norsett-Wanner initial step estimate with order 1.
+ *  Newton   At most 4 iterations on  dy - l_0 (h f(y0 + dy) - Z_1) = 0  with
+ *           M = I - gamma J and J taken at the prediction.  With d_m the norm of
+ *           the m-th correction and rho = d_m / d_{m-1}: converged when d_0 <= tau
+ *           or, later, rho < 1 and rho d_m / (1 - rho) <= tau; failed when rho >= 1
+ *           or rho^(4-m) d_m / (1 - rho) > tau (no convergence within 4), or on a
+ *           non-finite norm or a zero pivot.  tau = 0.03 (Hairer-Wanner kappa).
+ *  Error    E_q = |dy| / (q+1); a step is accepted when E_q <= 1.
+ *  Control  (order and step selection after the Nordsieck/LSODE family, with
+ *           biased estimates) After q+1 accepted steps at the same h and q, and
+ *           after every further step while nothing changes, form
+ *             E_{q-1} = (q-1)! |Z_q|,  E_q,  E_{q+1} = |dy - dy_prev| / (q+2),
+ *             eta_p = 1 / ((b_p E_p)^(1/(p+1)) + 1e-6),  b = 6, 6, 10;
+ *           take the largest (ties keep q, then prefer q-1); change nothing when
+ *           it is below 1.5, else eta = min(10, eta_p).  Order changes keep Z the
+ *           interpolant of the last accepted values (Stirling coefficients).
+ *  Failure  Newton failure: restore Z, h *= 0.25.  Error-test failure: restore Z,
+ *           eta = max(0.1, 1 / ((6 E_q)^(1/(q+1)) + 1e-6)); from the third
+ *           consecutive one, eta = 0.1 and the history restarts at order 1 from
+ *           f at the accepted state.  Ten consecutive failures of either kind end
+ *           the zone (CONV or ERRTEST); t + h == t ends it (HMIN); max_steps
+ *           accepted steps end it (MAXSTEPS); a non-finite start ends it
+ *           (NONFINITE).  A failed zone keeps its last accepted state.
+ *  End      The step that would reach dt (within 4 eps relative) is shortened
+ *           to land on dt exactly.
+ */
+#include <float.h>
+#include <math.h>
+#include <string.h>
+
+#include "oracle.h"
+
+typedef struct {
+    const orc_net *net;
+    const double *scale;
+    int nv;
+} sys_t;
+
+static double wrms(int nv, const double *v, const double *w)
+{
+    double s = 0.0;
+    for (int i = 0; i < nv; i++) {
+        double x = v[i] / w[i];
+        s += x * x;
+    }
+    return sqrt(s / nv);
+}
+
+/* Estimated local error of the accepted BDF-q step: dy ~ h^(q+1) y^(q+1), error constant 1/(q+1). */
+static double local_error(int nv, int q, const double *dy, const double *w)
+{
+    return wrms(nv, dy, w) / (q + 1);
+}
+
+static void rhs(const sys_t *S, const double *y, double *f, orc_stats *st)
+{
+    orc_rhs(S->net, S->scale, y, f);
+    st->nfe++;
+}
+
+/* l(q): prod_{i=1..q} (1 + x/i), normalised by its x coefficient (= H_q). */
+void orc_lcoef(int q, double *l)
+{
+    double p[ORC_QMAX + 2] = {1.0};
+    for (int i = 1; i <= q; i++) {
+        for (int j = i; j >= 1; j--) p[j] += p[j - 1] / i;
+    }
+    for (int j = 0; j <= q; j++) l[j] = p[j] / p[1];
+}
+
+/* c(n, j) = [x^j] x (x+1) ... (x+n-1)  (unsigned Stirling numbers of the first kind). */
+void orc_stirling(int n, double *c)
+{
+    double p[ORC_QMAX + 3] = {0.0};
+    p[1] = 1.0;                      /* the factor x */
+    for (int m = 1; m < n; m++) {    /* multiply by (x + m) */
+        for (int j = m + 1; j >= 1; j--) p[j] = p[j - 1] + m * p[j];
+        p[0] = m * p[0];
+    }
+    for (int j = 0; j <= n; j++) c[j] = p[j];
+}
+
+/* Raise q -> q+1: the new leading term is dy / (q+1)!, added along x(x+1)...(x+q). */
+void orc_order_raise(int nv, int q, double *Z, const double *dy)
+{
+    double c[ORC_QMAX + 3];
+    double fact = 1.0;
+    for (int i = 2; i <= q + 1; i++) fact *= i;
+    orc_stirling(q + 1, c);
+    double *Zn = Z + (size_t)(q + 1) * nv;
+    for (int i = 0; i < nv; i++) Zn[i] = dy[i] / fact;
+    for (int j = 1; j <= q; j++)
+        for (int i = 0; i < nv; i++) Z[(size_t)j * nv + i] += c[j] * Zn[i];
+}
+
+/* Lower q -> q-1: remove the leading term along x(x+1)...(x+q-1). */
+void orc_order_lower(int nv, int q, double *Z)
+{
+    double c[ORC_QMAX + 3];
+    orc_stirling(q, c);
+    const double *Zq = Z + (size_t)q * nv;
+    for (int j = 1; j < q; j++)
+        for (int i = 0; i < nv; i++) Z[(size_t)j * nv + i] -= c[j] * Zq[i];
+    for (int i = 0; i < nv; i++) Z[(size_t)q * nv + i] = 0.0;
+}
+
+static void rescale(int nv, int q, double *Z, double eta)
+{
+    double r = eta;
+    for (int j = 1; j <= q; j++) {
+        for (int i = 0; i < nv; i++) Z[(size_t)j * nv + i] *= r;
+        r *= eta;
+    }
+}
+
+static void predict(int nv, int q, double *Z)
+{
+    for (int k = 0; k < q; k++)
+        for (int j = q; j > k; j--)
+            for (int i = 0; i < nv; i++) Z[(size_t)(j - 1) * nv + i] += Z[(size_t)j * nv + i];
+}
+
+/* One Newton solve of the corrector.  On success dy holds y - y_pred and y the new value.
+   Returns 0 on convergence, 1 on failure. */
+static int newton(const sys_t *S, int q, double h, const double *Z, const double *w, double rtol,
+                  double *y, double *dy, orc_stats *st)
+{
+    int nv = S->nv;
+    double l[ORC_QMAX + 1], M[ORC_NVMAX * ORC_NVMAX], f[ORC_NVMAX], b[ORC_NVMAX];
+    int piv[ORC_NVMAX];
+    orc_lcoef(q, l);
+    double gamma = h * l[0];
+
+    orc_jac(S->net, S->scale, Z, M);
+    st->nje++;
+    for (int i = 0; i < nv; i++)
+        for (int j = 0; j < nv; j++) M[i * nv + j] = (i == j ? 1.0 : 0.0) - gamma * M[i * nv + j];
+    int sing = orc_lu(nv, M, piv);
+    st->nlu++;
+
+    const double tau = 0.03;
+    (void)rtol;
+    for (int i = 0; i < nv; i++) { y[i] = Z[i]; dy[i] = 0.0; }
+    double dprev = 0.0;
+    for (int m = 0; m < 4; m++) {
+        rhs(S, y, f, st);
+        for (int i = 0; i < nv; i++) b[i] = -(dy[i] - l[0] * (h * f[i] - Z[nv + i]));
+        if (sing) return 1;
+        orc_lu_solve(nv, M, piv, b);
+        for (int i = 0; i < nv; i++) { y[i] += b[i]; dy[i] += b[i]; }
+        double d = wrms(nv, b, w);
+        st->nni++;
+        if (!isfinite(d)) return 1;
+        if (m == 0) {
+            if (d <= tau) return 0;
+        } else {
+            double rho = d / dprev;
+            if (rho < 1.0 && rho * d / (1.0 - rho) <= tau) return 0;
+            if (rho >= 1.0 || pow(rho, 4 - m) * d / (1.0 - rho) > tau) return 1;
+        }
+        dprev = d;
+    }
+    return 1;
+}
+
+/* Corrector update of the history after an accepted step. */
+static void correct(int nv, int q, double *Z, const double *y, const double *dy)
+{
+    double l[ORC_QMAX + 1];
+    orc_lcoef(q, l);
+    for (int i = 0; i < nv; i++) {
+        double e = dy[i] / l[0];
+        for (int j = 1; j <= q; j++) Z[(size_t)j * nv + i] += l[j] * e;
+        Z[i] = y[i];
+    }
+}
+
+int orc_burn_zone(const orc_net *net, double *row, const double *scale, double dt, double rtol,
+                  double atol, int max_steps, orc_stats *st)
+{
+    sys_t S = {net, scale, orc_nvar(net)};
+    int nv = S.nv;
+    double Z[(ORC_QMAX + 2) * ORC_NVMAX], Zs[(ORC_QMAX + 2) * ORC_NVMAX];
+    double w[ORC_NVMAX], f0[ORC_NVMAX], f1[ORC_NVMAX], y1[ORC_NVMAX];
+    double y[ORC_NVMAX], dy[ORC_NVMAX], dyprev[ORC_NVMAX];
+    memset(st, 0, sizeof(*st));
+    memset(Z, 0, sizeof(Z));
+
+    /* ---- start: Hairer-Norsett-Wanner step estimate for order 1 ---- */
+    for (int i = 0; i < nv; i++) {
+        if (!isfinite(row[i])) return ORC_NONFINITE;
+        Z[i] = row[i];
+        w[i] = atol + rtol * fabs(row[i]);
+    }
+    rhs(&S, Z, f0, st);
+    for (int i = 0; i < nv; i++)
+        if (!isfinite(f0[i])) return ORC_NONFINITE;
+    double d0 = wrms(nv, Z, w), d1 = wrms(nv, f0, w);
+    double ha = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+    for (int i = 0; i < nv; i++) y1[i] = Z[i] + ha * f0[i];
+    rhs(&S, y1, f1, st);
+    for (int i = 0; i < nv; i++) dy[i] = f1[i] - f0[i];
+    double d2 = wrms(nv, dy, w) / ha;
+    double dm = fmax(d1, d2);
+    double hb = (dm <= 1e-15) ? fmax(1e-6, ha * 1e-3) : sqrt(0.01 / dm);
+    double h = fmin(fmin(100.0 * ha, hb), dt);
+    if (!isfinite(h) || !(h > 0.0)) return ORC_NONFINITE;
+
+    int q = 1, nequal = 0, nef = 0, ncf = 0, status = ORC_OK;
+    double t = 0.0;
+    for (int i = 0; i < nv; i++) { Z[nv + i] = h * f0[i]; dyprev[i] = 0.0; }
+
+    for (;;) {
+        if (st->nst >= max_steps) { status = ORC_MAXSTEPS; break; }
+        int last = 0;
+        if (t + h >= dt * (1.0 - 4.0 * DBL_EPSILON)) {
+            double eta = (dt - t) / h;
+            rescale(nv, q, Z, eta);
+            h = dt - t;
+            nequal = 0;
+            last = 1;
+        }
+        for (int i = 0; i < nv; i++) w[i] = atol + rtol * fabs(Z[i]);
+        memcpy(Zs, Z, sizeof(double) * (size_t)(q + 1) * nv);
+        predict(nv, q, Z);
+
+        if (newton(&S, q, h, Z, w, rtol, y, dy, st)) {
+            memcpy(Z, Zs, sizeof(double) * (size_t)(q + 1) * nv);
+            st->ncf++;
+            if (++ncf >= 10) { status = ORC_CONV; break; }
+            rescale(nv, q, Z, 0.25);
+            h *= 0.25;
+            nequal = 0;
+            if (t + h == t) { status = ORC_HMIN; break; }
+            continue;
+        }
+
+        double err = local_error(nv, q, dy, w);
+        if (err > 1.0) {
+            memcpy(Z, Zs, sizeof(double) * (size_t)(q + 1) * nv);
+            st->netf++;
+            if (++nef >= 10) { status = ORC_ERRTEST; break; }
+            double eta = fmax(0.1, 1.0 / (pow(6.0 * err, 1.0 / (q + 1)) + 1e-6));
+            if (nef >= 3) eta = 0.1;
+            h *= eta;
+            if (nef >= 3) {
+                q = 1;
+                rhs(&S, Z, f0, st);
+                for (int i = 0; i < nv; i++) Z[nv + i] = h * f0[i];
+            } else {
+                rescale(nv, q, Z, eta);
+            }
+            nequal = 0;
+            if (t + h == t) { status = ORC_HMIN; break; }
+            continue;
+        }
+
+        /* ---- accept ---- */
+        correct(nv, q, Z, y, dy);
+        t = last ? dt : t + h;
+        st->nst++;
+        nequal++;
+        nef = ncf = 0;
+        if (last) break;
+
+        if (nequal >= q + 1) {
+            double best = 1.0 / (pow(6.0 * err, 1.0 / (q + 1)) + 1e-6);
+            int qnew = q;
+            if (q > 1) {
+                double fact = 1.0;
+                for (int i = 2; i <= q - 1; i++) fact *= i;
+                double Em = fact * wrms(nv, Z + (size_t)q * nv, w);
+                double etam = 1.0 / (pow(6.0 * Em, 1.0 / q) + 1e-6);
+                if (etam > best) { best = etam; qnew = q - 1; }
+            }
+            if (q < ORC_QMAX) {
+                double dd[ORC_NVMAX];
+                for (int i = 0; i < nv; i++) dd[i] = dy[i] - dyprev[i];
+                double Ep = wrms(nv, dd, w) / (q + 2);
+                double etap = 1.0 / (pow(10.0 * Ep, 1.0 / (q + 2)) + 1e-6);
+                if (etap > best) { best = etap; qnew = q + 1; }
+            }
+            if (best >= 1.5) {
+                double eta = fmin(10.0, best);
+                if (qnew == q + 1) {
+                    orc_order_raise(nv, q, Z, dy);
+                    q++;
+                } else if (qnew == q - 1) {
+                    orc_order_lower(nv, q, Z);
+                    q--;
+                }
+                rescale(nv, q, Z, eta);
+                h *= eta;
+                nequal = 0;
+            }
+        }
+        for (int i = 0; i < nv; i++) dyprev[i] = dy[i];
+    }
+    for (int i = 0; i < nv; i++) row[i] = Z[i];
+    return status;
+}
+
+int orc_fixed_steps(const orc_net *net, const double *scale, int q, double h, int nsteps,
+                    double *Zio, double *ys, double *errs)
+{
+    sys_t S = {net, scale, orc_nvar(net)};
+    int nv = S.nv;
+    orc_stats st;
+    double Z[(ORC_QMAX + 2) * ORC_NVMAX], w[ORC_NVMAX], y[ORC_NVMAX], dy[ORC_NVMAX];
+    memset(&st, 0, sizeof(st));
+    memcpy(Z, Zio, sizeof(double) * (size_t)(q + 1) * nv);
+    for (int n = 0; n < nsteps; n++) {
+        for (int i = 0; i < nv; i++) w[i] = 1e-12 + 1e-8 * fabs(Z[i]);
+        predict(nv, q, Z);
+        if (newton(&S, q, h, Z, w, 1e-8, y, dy, &st)) return n + 1;
+        if (errs) errs[n] = local_error(nv, q, dy, w);
+        correct(nv, q, Z, y, dy);
+        for (int i = 0; i < nv; i++) ys[(size_t)n * nv + i] = Z[i];
+    }
+    memcpy(Zio, Z, sizeof(double) * (size_t)(q + 1) * nv);
+    return 0;
+}
+
+int orc_burn(const orc_net *net, double *state, int64_t zones, const double *scale, double dt,
+             double rtol, double atol, int max_steps, int32_t *status, int32_t *stats, int nthreads)
+{
+    if (orc_check_net(net)) return -1;
+    int row = net->ns + 1;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1) reduction(+ : bad)
+    for (int64_t z = 0; z < zones; z++) {
+        orc_stats st;
+        int s = orc_burn_zone(net, state + z * row, scale ? scale + z * net->nr : NULL, dt, rtol,
+                              atol, max_steps, &st);
+        if (status) status[z] = s;
+        if (stats) memcpy(stats + z * 7, &st, sizeof(st));
+        bad += (s != ORC_OK);
+    }
+    return bad;
+}

@@ -1,0 +1,456 @@
+"""Pins of the CPU oracle against what mathematics fixes independently of it.
+
+Each test checks the oracle against something other than itself: exact
+rationals from the definitions of the BDF and Stirling coefficients, the
+textbook fixed-step BDF formulas, complex-step derivatives, LAPACK's partial
+pivoting, closed-form solutions (matrix exponential of linear networks,
+two-body kinetics, first-order Arrhenius decay), conservation laws, an
+independent brute-force Radau IIA integrator and scipy's Radau at tight
+tolerance.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+from scipy.integrate import solve_ivp
+
+import oracle
+from paper_2608_06466_amd import workloads as W
+
+RTOL, ATOL = 1e-8, 1e-12
+
+
+def gated_err(y, ref, rtol=RTOL, atol=ATOL):
+    return float(np.max(np.abs(y - ref) / np.maximum(np.abs(ref), atol / rtol)))
+
+
+def linear_K(net):
+    ns = net["n_species"]
+    K = np.zeros((ns, ns))
+    for (a, _), (c, _), lk in zip(net["reactant"], net["product"], net["lnA"]):
+        k = math.exp(lk)
+        K[a, a] -= k
+        K[c, a] += k
+    return K
+
+
+# ---------------------------------------------------------------- coefficients
+
+def _poly_mul(p, r):
+    out = [Fraction(0)] * (len(p) + len(r) - 1)
+    for i, a in enumerate(p):
+        for j, b in enumerate(r):
+            out[i + j] += a * b
+    return out
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 4, 5])
+def test_lcoef_exact_rationals(q):
+    p = [Fraction(1)]
+    for i in range(1, q + 1):
+        p = _poly_mul(p, [Fraction(1), Fraction(1, i)])
+    exact = [c / p[1] for c in p]
+    got = oracle.lcoef(q)
+    for e, g in zip(exact, got):
+        assert abs(g - float(e)) <= 2 * np.spacing(float(e))
+    assert got[1] == 1.0
+    # l_0 is the reciprocal of the harmonic number H_q
+    assert abs(got[0] - 1.0 / sum(1.0 / i for i in range(1, q + 1))) < 1e-15
+
+
+def test_lcoef_printed_values():
+    # q = 2 and q = 5 written out
+    assert np.allclose(oracle.lcoef(2), [2 / 3, 1, 1 / 3], rtol=1e-15, atol=0)
+    assert np.allclose(oracle.lcoef(5), [60 / 137, 1, 225 / 274, 85 / 274, 15 / 274, 1 / 274],
+                       rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+def test_stirling_numbers(n):
+    c = oracle.stirling(n)
+    # sum_j c(n, j) = n!  and  c(n, 1) = (n-1)!, c(n, n) = 1, c(n, n-1) = n(n-1)/2
+    assert c.sum() == math.factorial(n)
+    assert c[1] == math.factorial(n - 1)
+    assert c[n] == 1
+    if n >= 2:
+        assert c[n - 1] == n * (n - 1) // 2
+    assert c[0] == 0
+
+
+# ---------------------------------------------------- Nordsieck == classic BDF
+
+def _nordsieck_of_interpolant(ys, xs):
+    """Coefficients (in x) of the polynomial of degree len(xs)-1 through (xs, ys)."""
+    V = np.vander(np.asarray(xs, dtype=float), len(xs), increasing=True)
+    return np.linalg.solve(V, ys)
+
+
+def _classic_bdf_alpha(q):
+    """alpha_j = derivative at x=1 of the Lagrange basis for nodes 1, 0, -1, ..., 1-q."""
+    nodes = [Fraction(1 - j) for j in range(q + 1)]
+    alpha = []
+    for j, xj in enumerate(nodes):
+        others = [xm for m, xm in enumerate(nodes) if m != j]
+        den = Fraction(1)
+        for xm in others:
+            den *= xj - xm
+        # d/dx prod (x - xm) at x = 1
+        s = Fraction(0)
+        for k in range(len(others)):
+            prod = Fraction(1)
+            for m, xm in enumerate(others):
+                if m != k:
+                    prod *= Fraction(1) - xm
+            s += prod
+        alpha.append(s / den)
+    return alpha
+
+
+def test_classic_bdf2_textbook_coefficients():
+    a = _classic_bdf_alpha(2)
+    a = [x / a[0] for x in a]
+    assert a == [1, Fraction(-4, 3), Fraction(1, 3)]
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 4, 5])
+def test_nordsieck_step_equals_classic_bdf(q):
+    net = W.linear_network(3, seed=11, k_range=(0.1, 10.0), density=1.0)
+    K = linear_K(net)
+    y0 = np.array([0.5, 0.3, 0.2])
+    h = 0.05
+    hist = np.array([sla.expm(K * (-i * h)) @ y0 for i in range(q + 1)])  # y_0, y_-1, ...
+    coef = _nordsieck_of_interpolant(hist, [-i for i in range(q + 1)])      # Z_j (x units)
+    nsteps = 25
+    ys, _ = oracle.fixed_steps(net, coef, q, h, nsteps)
+
+    alpha = [float(a) for a in _classic_bdf_alpha(q)]
+    seq = [hist[i] for i in range(q)][::-1]  # oldest .. newest (y_{1-q} .. y_0)
+    A = alpha[0] * np.eye(3) - h * K
+    ref = []
+    for n in range(nsteps):
+        rhs = -sum(alpha[j] * seq[-j] for j in range(1, q + 1))
+        ynew = np.linalg.solve(A, rhs)
+        seq.append(ynew)
+        ref.append(ynew)
+    ref = np.array(ref)
+    assert np.max(np.abs(ys - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 4, 5])
+def test_error_estimate_against_true_local_error(q):
+    """The estimate |dy|/(q+1) against the true local error of one step from exact history.
+
+    With exact past values the degree-q extrapolation misses y(t+h) by
+    h^(q+1) y^(q+1), and the BDF-q solution misses it by l_0 h^(q+1) y^(q+1)/(q+1)
+    (the first omitted term of sum_j (1/j) nabla^j, divided by H_q = 1/l_0).  So
+    dy = (1 + l_0/(q+1)) h^(q+1) y^(q+1) and, as h -> 0,
+        true local error / estimate  ->  (q+1) l_0 / (q+1+l_0).
+    """
+    k = 1.0
+    net = W.linear_network(2, seed=0, density=1.0)
+    net["reactant"] = np.array([[0, -1]], np.int32)
+    net["product"] = np.array([[1, -1]], np.int32)
+    for key in ("lnA", "n_exp", "E", "q"):
+        net[key] = np.zeros(1)
+    exact = lambda t: np.array([math.exp(-k * t), 1.0 - math.exp(-k * t)])
+    h = 0.01
+    hist = np.array([exact(-i * h) for i in range(q + 1)])
+    Z = _nordsieck_of_interpolant(hist, [-i for i in range(q + 1)])
+    ys, _, errs = oracle.fixed_steps(net, Z, q, h, 1, with_errors=True)
+    w = 1e-12 + 1e-8 * np.abs(hist[0])
+    true_err = math.sqrt(np.mean(((ys[0] - exact(h)) / w) ** 2))
+    l0 = 1.0 / sum(1.0 / i for i in range(1, q + 1))
+    expect = (q + 1) * l0 / (q + 1 + l0)
+    assert abs(true_err / errs[0] / expect - 1.0) < 0.03
+
+
+# ------------------------------------------------------------- order changes
+
+def _taylor(p_coef, t0, h):
+    """Coefficients in x of p(t0 + h x) for p given by increasing coefficients in t."""
+    P = np.polynomial.Polynomial(p_coef)
+    Q = P(np.polynomial.Polynomial([t0, h]))
+    return Q.coef
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 4])
+def test_order_raise_is_exact_on_polynomials(q):
+    rng = np.random.default_rng(q)
+    nv, h, tn = 3, 0.3, 1.7
+    polys = [rng.standard_normal(q + 2) for _ in range(nv)]  # degree q+1 per component
+    val = lambda t: np.array([np.polynomial.Polynomial(c)(t) for c in polys])
+    pts = [tn - i * h for i in range(q + 2)]                 # t_n .. t_{n-q-1}
+    ys = np.array([val(t) for t in pts])
+    # pi_n through y_n..y_{n-q}; pi_{n-1} through y_{n-1}..y_{n-q-1}, both in x = (t - t_n)/h
+    Zn = _nordsieck_of_interpolant(ys[: q + 1], [-i for i in range(q + 1)])
+    Zp = _nordsieck_of_interpolant(ys[1: q + 2], [-i for i in range(1, q + 2)])
+    dy = ys[0] - Zp[0]          # y_n minus the prediction pi_{n-1}(t_n)
+    Z = np.zeros((q + 2, nv))
+    Z[: q + 1] = Zn
+    got = oracle.order_raise(Z, q, dy)
+    want = np.array([_taylor(c, tn, h) for c in polys]).T   # [q+2][nv]
+    assert np.allclose(got, want, rtol=0, atol=1e-10 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("q", [2, 3, 4, 5])
+def test_order_lower_is_exact_on_polynomials(q):
+    rng = np.random.default_rng(10 + q)
+    nv, h, tn = 2, 0.2, -0.4
+    ys = rng.standard_normal((q + 1, nv))                     # values at t_n .. t_{n-q}
+    Zq = _nordsieck_of_interpolant(ys, [-i for i in range(q + 1)])
+    got = oracle.order_lower(Zq, q)
+    want = np.zeros_like(Zq)
+    want[:q] = _nordsieck_of_interpolant(ys[:q], [-i for i in range(q)])
+    assert np.allclose(got, want, rtol=0, atol=1e-11 * np.abs(Zq).max())
+
+
+# ------------------------------------------------------------ RHS / Jacobian
+
+def _nets():
+    yield "robertson", W.robertson_network(), np.array([0.7, 3e-5, 0.3, 0.0])
+    n2 = W.config2_network()
+    st = W.random_zones(n2, 3, seed=5)
+    yield "config2", n2, st[1]
+    n3 = W.random_network(21, 50, 302)
+    yield "net22", n3, W.random_zones(n3, 2, seed=6)[0]
+    yield "linear", W.linear_network(5, 3), np.array([0.1, 0.2, 0.3, 0.15, 0.25, 0.0])
+    yield "aa", W.two_body_network(2.0, same=True), np.array([0.4, 0.0, 0.3, 0.3, 0.0])
+
+
+@pytest.mark.parametrize("name,net,y", list(_nets()), ids=[n for n, _, _ in _nets()])
+def test_jacobian_equals_complex_step_derivative(name, net, y):
+    n = oracle.Net(net)
+    y = np.asarray(y, dtype=float)[: n.nv]
+    J = oracle.jac(n, y)
+    eps = 1e-30
+    Jcs = np.zeros_like(J)
+    for j in range(n.nv):
+        yc = y.astype(complex)
+        yc[j] += 1j * eps * max(1.0, abs(y[j]))
+        Jcs[:, j] = oracle.rhs_complex(n, yc).imag / (eps * max(1.0, abs(y[j])))
+    np.testing.assert_allclose(J, Jcs, rtol=1e-12, atol=1e-14 * np.abs(J).max())
+    # the real part of the complex evaluation is the real right-hand side
+    assert np.allclose(oracle.rhs_complex(n, y.astype(complex)).real, oracle.rhs(n, y),
+                       rtol=1e-15, atol=0)
+
+
+def test_rhs_conserves_species_and_energy():
+    n2 = W.config2_network()
+    for y in W.random_zones(n2, 5, seed=9):
+        f = oracle.rhs(n2, y)
+        assert abs(f[:13].sum()) <= 1e-13 * np.abs(f[:13]).max()
+    net, B = W.energy_test_network(8, 20, seed=4)
+    for y in W.random_zones(net, 5, seed=3, T_range=(500, 900)):
+        f = oracle.rhs(net, y)
+        assert abs(f[-1] + B @ f[:-1]) <= 1e-12 * (abs(f[-1]) + np.abs(B * f[:-1]).sum())
+
+
+def test_arrhenius_rate_first_order_decay():
+    """A -> B with k = A T^n exp(-E/T) at fixed T (q = 0): Y_A(t) = Y_A(0) exp(-k t)."""
+    A, nexp, E, T = 3.0e4, 0.7, 2.0e3, 900.0
+    net = {"n_species": 2, "thermal": 1, "reactant": np.array([[0, -1]], np.int32),
+           "product": np.array([[1, -1]], np.int32), "lnA": np.array([math.log(A)]),
+           "n_exp": np.array([nexp]), "E": np.array([E]), "q": np.array([0.0])}
+    k = A * T ** nexp * math.exp(-E / T)
+    dt = 3.0 / k
+    st, status, _ = oracle.burn(net, np.array([[0.8, 0.2, T]]), dt, RTOL, ATOL)
+    ya = 0.8 * math.exp(-k * dt)
+    assert status[0] == 0
+    assert gated_err(st[0, :2], np.array([ya, 1.0 - ya])) < 1e-6
+    assert st[0, 2] == T
+
+
+# ------------------------------------------------------------------------ LU
+
+def test_lu_pivots_match_lapack():
+    rng = np.random.default_rng(0)
+    for n in (3, 14, 22, 48):
+        A = rng.standard_normal((n, n)) * np.exp(rng.uniform(-5, 5, (n, 1)))
+        LU, piv, info = oracle.lu(A)
+        lu2, piv2 = sla.lu_factor(A)
+        assert info == 0
+        assert np.array_equal(piv, piv2)
+        np.testing.assert_allclose(LU, lu2, rtol=1e-10, atol=1e-12 * np.abs(lu2).max())
+        b = rng.standard_normal(n)
+        x = oracle.lu_solve(LU, piv, b)
+        np.testing.assert_allclose(A @ x, b, rtol=0, atol=1e-10 * np.abs(A).max() * np.abs(x).max())
+
+
+def test_lu_ties_choose_lowest_row():
+    A = np.array([[1.0, 2.0, 0.0], [-3.0, 1.0, 1.0], [3.0, 0.5, 2.0]])
+    _, piv, _ = oracle.lu(A)
+    assert piv[0] == 1          # |-3| == |3|: the first row with the maximum
+
+
+def test_lu_zero_pivot_reported():
+    A = np.array([[1.0, 2.0], [2.0, 4.0]])
+    _, _, info = oracle.lu(A)
+    assert info == 2
+
+
+# ------------------------------------------------------- whole-integrator pins
+
+@pytest.mark.parametrize("seed", range(6))
+def test_linear_network_matches_matrix_exponential(seed):
+    ns = 4 + seed % 3
+    net = W.linear_network(ns, seed)
+    K = linear_K(net)
+    y0 = np.random.default_rng(seed).dirichlet(np.ones(ns))
+    st = np.zeros((1, ns + 1))
+    st[0, :ns] = y0
+    out, status, _ = oracle.burn(net, st, 10.0, RTOL, ATOL)
+    assert status[0] == 0
+    assert gated_err(out[0, :ns], sla.expm(K * 10.0) @ y0) < 1e-6
+
+
+def test_two_body_closed_forms():
+    k = 5.0
+    ya, yb = 0.6, 0.25
+    net = W.two_body_network(k)
+    dt = 2.0
+    out, status, _ = oracle.burn(net, np.array([[ya, yb, 0.05, 0.1, 0.0]]), dt, RTOL, ATOL)
+    d = ya - yb
+    YB = d * yb / (ya * math.exp(k * d * dt) - yb)
+    YA = YB + d
+    ref = np.array([YA, YB, 0.05 + (yb - YB), 0.1 + (yb - YB)])
+    assert status[0] == 0 and gated_err(out[0, :4], ref) < 1e-6
+
+    net = W.two_body_network(k, same=True)
+    out, status, _ = oracle.burn(net, np.array([[ya, 0.0, 0.0, 0.0, 0.0]]), dt, RTOL, ATOL)
+    YA = ya / (1 + 2 * k * ya * dt)
+    ref = np.array([YA, 0.0, (ya - YA) / 2, (ya - YA) / 2])
+    assert status[0] == 0 and gated_err(out[0, :4], ref) < 1e-6
+
+
+def test_species_sum_invariant_on_benchmark_networks():
+    c2 = W.config2(64)
+    out, status, _ = oracle.burn(c2["net"], c2["state"], c2["dt"], RTOL, ATOL)
+    assert np.all(status == 0)
+    drift = np.abs(out[:, :13].sum(1) - c2["state"][:, :13].sum(1))
+    assert drift.max() < 1e-12
+    c1 = W.config1(16)
+    out, status, _ = oracle.burn(c1["net"], c1["state"], c1["dt"], RTOL, ATOL, c1["scale"])
+    assert np.all(status == 0)
+    assert np.abs(out[:, :3].sum(1) - 1.0).max() < 1e-12
+
+
+def test_energy_invariant():
+    net, B = W.energy_test_network(8, 20, seed=4)
+    st = W.random_zones(net, 8, seed=3, T_range=(500, 900))
+    out, status, _ = oracle.burn(net, st, 1.0, RTOL, ATOL)
+    assert np.all(status == 0)
+    e0 = st[:, -1] + st[:, :-1] @ B
+    e1 = out[:, -1] + out[:, :-1] @ B
+    assert np.abs(e1 - e0).max() < 1e-11 * np.abs(e0).max()
+    assert np.abs(out[:, -1] - st[:, -1]).max() > 1e-6   # T really moved
+
+
+# ------------------------------------------------------ brute force: Radau IIA
+
+def test_radau_is_third_order():
+    net = W.two_body_network(3.0)
+    y0 = np.array([0.6, 0.25, 0.05, 0.1, 0.0])
+    dt = 1.0
+    d = 0.35
+    YB = d * 0.25 / (0.6 * math.exp(3.0 * d * dt) - 0.25)
+    errs = [abs(oracle.radau(net, y0, dt, n)[1] - YB) for n in (20, 40, 80)]
+    ratios = [errs[0] / errs[1], errs[1] / errs[2]]
+    assert all(6.5 < r < 9.5 for r in ratios), ratios
+
+
+def test_radau_matches_matrix_exponential():
+    net = W.linear_network(5, 2)
+    K = linear_K(net)
+    y0 = np.random.default_rng(2).dirichlet(np.ones(5))
+    ref = sla.expm(K * 10.0) @ y0
+    y1 = oracle.radau(net, np.append(y0, 0.0), 10.0, 4000, h0=1e-12)
+    y2 = oracle.radau(net, np.append(y0, 0.0), 10.0, 8000, h0=1e-12)
+    e1, e2 = gated_err(y1, ref), gated_err(y2, ref)
+    assert e2 < 1e-7 and 6.0 < e1 / e2 < 10.0        # third order on the graded mesh
+    assert gated_err(y2 + (y2 - y1) / 7.0, ref) < 1e-9
+
+
+def _radau_converged(net, y0, dt, n0, h0, scale=None):
+    prev = oracle.radau(net, y0, dt, n0, h0, scale)
+    cur = oracle.radau(net, y0, dt, 2 * n0, h0, scale)
+    est = cur + (cur - prev) / 7.0   # Richardson for order 3
+    return est, gated_err(cur, est)
+
+
+@pytest.mark.slow
+def test_bdf_matches_bruteforce_radau_tiny_batch():
+    c1 = W.config1(2)
+    out, status, _ = oracle.burn(c1["net"], c1["state"], c1["dt"], RTOL, ATOL, c1["scale"])
+    for z in range(2):
+        ref, conv = _radau_converged(c1["net"], c1["state"][z], c1["dt"], 20000, 1e-9, c1["scale"][z])
+        assert conv < 1e-8
+        assert gated_err(out[z, :3], ref) < 1e-6
+    c2 = W.config2(1)
+    out, status, _ = oracle.burn(c2["net"], c2["state"], c2["dt"], RTOL, ATOL)
+    ref, conv = _radau_converged(c2["net"], c2["state"][0], 1.0, 20000, 1e-17)
+    assert conv < 1e-7
+    assert gated_err(out[0, :14], ref) < 1e-6
+
+
+@pytest.mark.slow
+def test_robertson_matches_scipy_radau():
+    net = oracle.Net(W.robertson_network())
+    sol = solve_ivp(lambda t, y: oracle.rhs(net, y), (0, 1e5), [1.0, 0.0, 0.0], method="Radau",
+                    rtol=1e-12, atol=1e-20, jac=lambda t, y: oracle.jac(net, y))
+    out, status, _ = oracle.burn(net, np.array([[1.0, 0.0, 0.0, 0.0]]), 1e5, RTOL, ATOL)
+    assert status[0] == 0
+    assert gated_err(out[0, :3], sol.y[:, -1]) < 1e-6
+
+
+@pytest.mark.slow
+def test_config2_zones_match_scipy_radau():
+    c2 = W.config2(2)
+    net = oracle.Net(c2["net"])
+    out, status, _ = oracle.burn(net, c2["state"], 1.0, RTOL, ATOL)
+    for z in (1,):
+        sol = solve_ivp(lambda t, y: oracle.rhs(net, y), (0, 1.0), c2["state"][z], method="Radau",
+                        rtol=1e-12, atol=1e-18, jac=lambda t, y: oracle.jac(net, y))
+        assert status[z] == 0
+        assert gated_err(out[z], sol.y[:, -1]) < 1e-6
+
+
+# ------------------------------------------------------------------- statuses
+
+def test_status_codes():
+    c2 = W.config2(4)
+    net = c2["net"]
+    out, status, stats = oracle.burn(net, c2["state"], 1.0, RTOL, ATOL, max_steps=5)
+    assert np.all(status == 1) and np.all(stats[:, 0] == 5)
+    assert np.all(np.isfinite(out))
+    bad = c2["state"].copy()
+    bad[0, 3] = np.nan
+    bad[1, -1] = -50.0          # negative temperature: log(T) is not finite
+    out, status, _ = oracle.burn(net, bad, 1.0, RTOL, ATOL)
+    assert status[0] == 5 and status[1] == 5 and status[2] == 0
+    assert np.array_equal(out[1], bad[1])
+    out, status, _ = oracle.burn(net, c2["state"][:1], 1.0, 1e-30, 1e-40, max_steps=3000)
+    assert status[0] != 0
+    out, status, _ = oracle.burn(net, np.zeros((0, 14)), 1.0, RTOL, ATOL)
+    assert out.shape == (0, 14)
+
+
+def test_counter_consistency():
+    c2 = W.config2(16)
+    _, status, stats = oracle.burn(c2["net"], c2["state"], 1.0, RTOL, ATOL)
+    nst, nfe, nje, nlu, nni, netf, ncf = stats.T
+    assert np.array_equal(nje, nlu)
+    assert np.all(nje == nst + netf + ncf)          # one Jacobian per step attempt
+    assert np.all(nfe >= nni + 2)                    # start costs two evaluations
+    assert np.all(nni <= 4 * nje)
+
+
+def test_step_counts_comparable_to_scipy_bdf():
+    c2 = W.config2(2)
+    net = oracle.Net(c2["net"])
+    _, _, stats = oracle.burn(net, c2["state"], 1.0, RTOL, ATOL)
+    for z in range(2):
+        sol = solve_ivp(lambda t, y: oracle.rhs(net, y), (0, 1.0), c2["state"][z], method="BDF",
+                        rtol=RTOL, atol=ATOL, jac=lambda t, y: oracle.jac(net, y))
+        assert 0.33 < stats[z, 0] / (sol.t.size - 1) < 3.0
