@@ -1,0 +1,150 @@
+/*
+ * zoneburn: per-zone stiff reaction-network burn on MI355X (gfx950).
+ *
+ * What is computed.  The paper ("Software design" section) describes
+ * microphysics routines written for a single zone and looped over the zones of
+ * a simulation, state kept in GPU memory for the whole run, a compile-time
+ * selected reaction network that fixes the composition, a VODE-type stiff
+ * integrator, and a step cap after which a failing zone is reported back to the
+ * application instead of stopping the run.  zb_burn is that loop: every zone
+ * independently integrates y' = f(y) over [0, dt], where y holds the species
+ * abundances (and the temperature for a network with self-heating), with a
+ * variable-order (1..5) BDF method in Nordsieck form, Newton iteration on a
+ * dense LU of M = I - gamma J with the analytic Jacobian, and weighted-RMS
+ * error, order and step control.  Zones never communicate.
+ *
+ * Conventions.  Every function returns a zb_err; nothing else crosses the
+ * ABI.  Pointers documented as DEVICE must be device (or managed) memory of the
+ * context's GPU; HOST pointers are ordinary host memory.  The caller owns every
+ * buffer it passes; the library owns networks, servers and its workspaces.
+ * Calls on one context from several host threads are safe except where noted.
+ */
+#ifndef ZONEBURN_H
+#define ZONEBURN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ZB_OK = 0,
+    ZB_EINVAL = 1,     /* bad argument; nothing was launched */
+    ZB_ENOMEM = 2,     /* device or host allocation failed */
+    ZB_EDEVICE = 3,    /* HIP runtime error (launch, copy, synchronize) */
+    ZB_EZONES = 4,     /* zb_sync: at least one zone ended with a non-OK status */
+    ZB_EBUSY = 5,      /* server: pending queue full */
+    ZB_ENOTFOUND = 6,  /* server: unknown ticket */
+    ZB_EUNSUPPORTED = 7 /* no kernel for this (network size, mapping, precision) */
+} zb_err;
+
+/* Per-zone outcome (the paper: cap the steps and pass failures back). */
+typedef enum {
+    ZB_ZONE_OK = 0,
+    ZB_ZONE_MAXSTEPS = 1,   /* max_steps accepted steps did not reach dt */
+    ZB_ZONE_ERRTEST = 2,    /* ten consecutive error-test failures */
+    ZB_ZONE_CONV = 3,       /* ten consecutive Newton failures */
+    ZB_ZONE_HMIN = 4,       /* step size fell below the resolution of t */
+    ZB_ZONE_NONFINITE = 5   /* non-finite initial state or right-hand side */
+} zb_zone_status;
+
+/* Per-zone counters: accepted steps, RHS evaluations, Jacobians, LU factorizations,
+   Newton iterations, error-test failures, Newton (convergence) failures. */
+typedef struct { int32_t nst, nfe, nje, nlu, nni, netf, ncf; } zb_zone_stats;
+
+/* Mass-action network with Arrhenius rates (the paper: a network, selected by the
+   user, defines the composition).  Reaction r consumes reactant[r][0] and, unless it
+   is -1, reactant[r][1]; it produces product[r][0] and, unless -1, product[r][1].
+   Rate  k_r = exp(lnA + n ln T - E / T) * scale  when thermal, else exp(lnA) * scale;
+   w_r = k_r Y_a Y_b (k_r Y_a for one reactant).  dY_i/dt = sum_r nu_ir w_r and, when
+   thermal, dT/dt = sum_r q_r w_r.  Arrays are HOST pointers, copied by zb_network_create. */
+typedef struct {
+    int32_t n_species;         /* 1 .. 64 (63 when thermal) */
+    int32_t thermal;           /* 0: T is passed through unchanged; 1: T is integrated */
+    int32_t n_reactions;       /* 0 .. 4096 */
+    const int32_t *reactant;   /* [n_reactions][2] */
+    const int32_t *product;    /* [n_reactions][2] */
+    const double *lnA, *n_exp, *E, *q;   /* [n_reactions] each; q unused unless thermal */
+} zb_network_desc;
+
+typedef struct zb_context zb_context;
+typedef struct zb_network zb_network;
+typedef struct zb_server zb_server;
+
+enum { ZB_FP64 = 0, ZB_MIXED = 1 };               /* zb_opts.precision */
+enum { ZB_MAP_AUTO = 0 };                          /* zb_opts.mapping: else lanes per zone 1..64 */
+
+typedef struct {
+    int32_t max_steps;   /* accepted steps per zone before ZB_ZONE_MAXSTEPS (<= 0: 100000) */
+    int32_t precision;   /* ZB_FP64: everything in FP64.  ZB_MIXED: the iteration-matrix LU and
+                            its triangular solves in FP32 (rows and columns scaled by the error
+                            weights); RHS, Jacobian, residual, update, norms and control in FP64 */
+    int32_t mapping;     /* ZB_MAP_AUTO or lanes per zone (1, 2, 4, 8, 16, 32, 64) */
+    int32_t reserved;
+} zb_opts;
+
+/* Create a context on HIP device `device` (allocates a small device workspace). */
+zb_err zb_context_create(int device, zb_context **out);
+zb_err zb_context_destroy(zb_context *ctx);
+
+/* Copy a network to the device and precompute its per-row evaluation tables.
+   ZB_EINVAL on out-of-range sizes or indices. */
+zb_err zb_network_create(zb_context *ctx, const zb_network_desc *desc, zb_network **out);
+zb_err zb_network_destroy(zb_network *net);
+/* Number of integrated variables (n_species + thermal) and reactions. */
+zb_err zb_network_info(const zb_network *net, int32_t *n_var, int32_t *n_reactions);
+
+/* Burn `zones` zones in place over [0, dt] (the operator-split burn of one hydro step).
+   state       DEVICE, row-major [zones][n_species + 1]: abundances, then T.  On return every
+               zone holds its final state, or its last accepted state if it failed.
+   rate_scale  DEVICE [zones][n_reactions] multipliers of k_r, or NULL for 1.
+   zone_status DEVICE [zones] zb_zone_status, or NULL.
+   stats       DEVICE [zones] counters, or NULL.
+   stream      hipStream_t (as void*), NULL for the null stream.  The call is asynchronous:
+               argument errors return at once, everything else surfaces in zb_sync.
+   ZB_EINVAL: zones < 0, dt not finite or <= 0, rtol <= 0, atol <= 0 (or not finite),
+   NULL state with zones > 0, or buffers of another device. */
+zb_err zb_burn(zb_context *ctx, const zb_network *net, double *state, int64_t zones, double dt,
+               double rtol, double atol, const double *rate_scale, const zb_opts *opts,
+               int32_t *zone_status, zb_zone_stats *stats, void *stream);
+
+/* Wait for `stream` and report: ZB_OK, ZB_EDEVICE, or ZB_EZONES if any zone of any burn on
+   this context since the previous zb_sync ended with a non-OK status (the count is cleared). */
+zb_err zb_sync(zb_context *ctx, void *stream, int64_t *n_failed_zones);
+
+/* Several networks in ONE persistent launch (zones of uneven cost and different sizes share a
+   device work queue).  Each segment is burned exactly as zb_burn would burn it alone with the
+   same opts and lanes per zone. */
+typedef struct {
+    const zb_network *net;
+    double *state;              /* DEVICE [zones][n_species+1] */
+    int64_t zones;
+    double dt, rtol, atol;
+    const double *rate_scale;   /* DEVICE or NULL */
+    int32_t *zone_status;       /* DEVICE or NULL */
+    zb_zone_stats *stats;       /* DEVICE or NULL */
+} zb_segment;
+zb_err zb_burn_batch(zb_context *ctx, const zb_segment *segs, int32_t n_seg, const zb_opts *opts,
+                     void *stream);
+
+/* Lanes per zone the library uses for (network, precision) when opts->mapping is AUTO. */
+zb_err zb_get_mapping(zb_context *ctx, const zb_network *net, int32_t precision, int32_t *lanes);
+/* Time every supported mapping on a DEVICE sample state [zones][ns+1] (copied, not modified),
+   keep the fastest whose results agree with the first candidate's, and use it from now on.
+   Results are cached per (network size, reactions, precision, device) in the file named by
+   ZB_AUTOTUNE_CACHE, if set.  times_ms (HOST, optional) receives one entry per lane count
+   1,2,4,...,64 (negative when unsupported). */
+zb_err zb_autotune(zb_context *ctx, const zb_network *net, const double *sample_state,
+                   int64_t zones, double dt, double rtol, double atol, int32_t precision,
+                   int32_t *best_lanes, float *times_ms);
+
+/* Human-readable name of an error code and the last error message of this thread. */
+const char *zb_strerror(zb_err err);
+const char *zb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ZONEBURN_H */

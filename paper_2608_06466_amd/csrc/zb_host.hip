@@ -1,0 +1,522 @@
+// Host runtime of libzoneburn: contexts, device copies of networks, kernel
+// selection, launch configuration and the C ABI declared in include/zoneburn.h.
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "zb_internal.h"
+#include "zoneburn.h"
+
+using namespace zb;
+
+static thread_local std::string g_last_error;
+
+static zb_err fail(zb_err e, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return e;
+}
+
+#define HIP_TRY(call)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(ZB_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));        \
+    } while (0)
+
+namespace {
+constexpr int QUEUE_SLOTS = 1024;
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+}  // namespace
+
+struct zb_context {
+    int device = 0;
+    int cus = 0;
+    unsigned long long *ws = nullptr;   // [0] failed zones, then QUEUE_SLOTS x MAXSEG queue counters
+    int next_slot = 0;
+    std::mutex mu;
+    // autotuned lanes per zone, keyed by (nv, nr, precision)
+    struct Tuned { int nv, nr, prec, lanes; };
+    std::vector<Tuned> tuned;
+};
+
+struct zb_network {
+    zb_context *ctx = nullptr;
+    DevNet dn{};
+    void *dmem = nullptr;
+};
+
+// ------------------------------------------------------------------ context
+
+extern "C" zb_err zb_context_create(int device, zb_context **out)
+{
+    if (!out) return fail(ZB_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(ZB_EINVAL, "device %d out of range (%d devices)", device, n);
+    DeviceGuard g(device);
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(ZB_EUNSUPPORTED, "device %d is %s; the kernels are built for gfx950", device,
+                    prop.gcnArchName);
+    zb_context *c = new (std::nothrow) zb_context();
+    if (!c) return fail(ZB_ENOMEM, "host allocation failed");
+    c->device = device;
+    c->cus = prop.multiProcessorCount;
+    if (hipMalloc((void **)&c->ws, sizeof(unsigned long long) * (1 + QUEUE_SLOTS * MAXSEG)) != hipSuccess) {
+        delete c;
+        return fail(ZB_ENOMEM, "workspace allocation failed");
+    }
+    if (launch_reset(c->ws, 1 + QUEUE_SLOTS * MAXSEG, nullptr) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(c->ws);
+        delete c;
+        return fail(ZB_EDEVICE, "workspace initialisation failed");
+    }
+    *out = c;
+    return ZB_OK;
+}
+
+extern "C" zb_err zb_context_destroy(zb_context *ctx)
+{
+    if (!ctx) return ZB_OK;
+    {
+        DeviceGuard g(ctx->device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ctx->ws);
+    }
+    delete ctx;
+    return ZB_OK;
+}
+
+// ------------------------------------------------------------------ network
+
+extern "C" zb_err zb_network_create(zb_context *ctx, const zb_network_desc *d, zb_network **out)
+{
+    if (!ctx || !d || !out) return fail(ZB_EINVAL, "NULL argument");
+    *out = nullptr;
+    const int ns = d->n_species, nr = d->n_reactions, th = d->thermal ? 1 : 0;
+    const int nv = ns + th;
+    if (ns < 1 || nv > NVMAX) return fail(ZB_EINVAL, "n_species %d: need 1 <= n_species + thermal <= %d", ns, NVMAX);
+    if (nr < 0 || nr > RMAX) return fail(ZB_EINVAL, "n_reactions %d out of range 0..%d", nr, RMAX);
+    if (nr > 0 && (!d->reactant || !d->product || !d->lnA || !d->n_exp || !d->E || (th && !d->q)))
+        return fail(ZB_EINVAL, "NULL reaction array");
+    std::vector<int4> rct(std::max(nr, 1));
+    std::vector<double4> par(std::max(nr, 1));
+    for (int r = 0; r < nr; ++r) {
+        int a = d->reactant[2 * r], b = d->reactant[2 * r + 1];
+        int c = d->product[2 * r], e = d->product[2 * r + 1];
+        if (a < 0 || a >= ns || b < -1 || b >= ns || c < 0 || c >= ns || e < -1 || e >= ns)
+            return fail(ZB_EINVAL, "reaction %d: species index out of range", r);
+        double q = th ? d->q[r] : 0.0;
+        if (!isfinite(d->lnA[r]) || !isfinite(d->n_exp[r]) || !isfinite(d->E[r]) || !isfinite(q))
+            return fail(ZB_EINVAL, "reaction %d: non-finite parameter", r);
+        rct[r] = make_int4(a, b, c, e);
+        par[r] = make_double4(d->lnA[r], d->n_exp[r], d->E[r], q);
+    }
+    // per-species involvement lists (net stoichiometry != 0) and reactant lists
+    std::vector<std::vector<int>> inv(ns), rea(ns);
+    for (int r = 0; r < nr; ++r) {
+        const int4 x = rct[r];
+        for (int i = 0; i < ns; ++i) {
+            int nu = (x.z == i) + (x.w == i) - (x.x == i) - (x.y == i);
+            if (nu != 0) inv[i].push_back(r | ((nu + 8) << 16));
+            int fl = (x.x == i ? 1 : 0) | (x.y == i ? 2 : 0);
+            if (fl) rea[i].push_back(r | (fl << 16));
+        }
+    }
+    int inv_len = 1, rea_len = 1;
+    for (int i = 0; i < ns; ++i) {
+        inv_len = std::max<int>(inv_len, (int)inv[i].size());
+        rea_len = std::max<int>(rea_len, (int)rea[i].size());
+    }
+    std::vector<int> invf((size_t)ns * inv_len, -1), reaf((size_t)ns * rea_len, -1);
+    for (int i = 0; i < ns; ++i) {
+        std::copy(inv[i].begin(), inv[i].end(), invf.begin() + (size_t)i * inv_len);
+        std::copy(rea[i].begin(), rea[i].end(), reaf.begin() + (size_t)i * rea_len);
+    }
+    size_t o_rct = 0, o_par = o_rct + sizeof(int4) * rct.size();
+    size_t o_inv = o_par + sizeof(double4) * par.size();
+    size_t o_rea = o_inv + sizeof(int) * invf.size();
+    size_t bytes = o_rea + sizeof(int) * reaf.size();
+    zb_network *n = new (std::nothrow) zb_network();
+    if (!n) return fail(ZB_ENOMEM, "host allocation failed");
+    DeviceGuard g(ctx->device);
+    char *dm = nullptr;
+    if (hipMalloc((void **)&dm, bytes) != hipSuccess) {
+        delete n;
+        return fail(ZB_ENOMEM, "device allocation of %zu bytes failed", bytes);
+    }
+    std::vector<char> host(bytes);
+    memcpy(host.data() + o_rct, rct.data(), sizeof(int4) * rct.size());
+    memcpy(host.data() + o_par, par.data(), sizeof(double4) * par.size());
+    memcpy(host.data() + o_inv, invf.data(), sizeof(int) * invf.size());
+    memcpy(host.data() + o_rea, reaf.data(), sizeof(int) * reaf.size());
+    if (hipMemcpy(dm, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(dm);
+        delete n;
+        return fail(ZB_EDEVICE, "copy of the network to the device failed");
+    }
+    n->ctx = ctx;
+    n->dmem = dm;
+    n->dn.ns = ns;
+    n->dn.nv = nv;
+    n->dn.thermal = th;
+    n->dn.nr = nr;
+    n->dn.inv_len = inv_len;
+    n->dn.rea_len = rea_len;
+    n->dn.rct = (const int4 *)(dm + o_rct);
+    n->dn.par = (const double4 *)(dm + o_par);
+    n->dn.inv = (const int *)(dm + o_inv);
+    n->dn.rea = (const int *)(dm + o_rea);
+    *out = n;
+    return ZB_OK;
+}
+
+extern "C" zb_err zb_network_destroy(zb_network *n)
+{
+    if (!n) return ZB_OK;
+    {
+        DeviceGuard g(n->ctx->device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(n->dmem);
+    }
+    delete n;
+    return ZB_OK;
+}
+
+extern "C" zb_err zb_network_info(const zb_network *n, int32_t *n_var, int32_t *n_reactions)
+{
+    if (!n) return fail(ZB_EINVAL, "NULL network");
+    if (n_var) *n_var = n->dn.nv;
+    if (n_reactions) *n_reactions = n->dn.nr;
+    return ZB_OK;
+}
+
+// ------------------------------------------------------------- kernel choice
+
+static int default_lanes(int nv)
+{
+    if (nv <= 4) return 1;
+    if (nv <= 8) return 8;
+    if (nv <= 16) return 16;
+    if (nv <= 32) return 32;
+    return 64;
+}
+
+// Smallest kernel with nvp >= nv for the given lanes and precision.
+static const KernelInfo *find_kernel(int nv, int lanes, int mixed)
+{
+    const KernelInfo *tab;
+    int n = kernel_table(&tab);
+    const KernelInfo *best = nullptr;
+    for (int i = 0; i < n; ++i) {
+        if (tab[i].lanes != lanes || tab[i].mixed != mixed || tab[i].nvp < nv) continue;
+        if (!best || tab[i].nvp < best->nvp) best = &tab[i];
+    }
+    return best;
+}
+
+static int lanes_for(zb_context *ctx, const zb_network *net, int prec, const zb_opts *o)
+{
+    if (o && o->mapping != ZB_MAP_AUTO) return o->mapping;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (auto &t : ctx->tuned)
+        if (t.nv == net->dn.nv && t.nr == net->dn.nr && t.prec == prec) return t.lanes;
+    return default_lanes(net->dn.nv);
+}
+
+extern "C" zb_err zb_get_mapping(zb_context *ctx, const zb_network *net, int32_t precision, int32_t *lanes)
+{
+    if (!ctx || !net || !lanes) return fail(ZB_EINVAL, "NULL argument");
+    *lanes = lanes_for(ctx, net, precision, nullptr);
+    return ZB_OK;
+}
+
+// ------------------------------------------------------------------- launch
+
+static bool valid_ptr(const void *p, int device)
+{
+    if (!p) return true;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) return a.device == device;
+    return false;
+}
+
+static zb_err check_segment(zb_context *ctx, const zb_segment &s)
+{
+    if (!s.net) return fail(ZB_EINVAL, "NULL network");
+    if (s.net->ctx != ctx) return fail(ZB_EINVAL, "network belongs to another context");
+    if (s.zones < 0) return fail(ZB_EINVAL, "zones < 0");
+    if (!(isfinite(s.dt) && s.dt > 0.0)) return fail(ZB_EINVAL, "dt must be finite and > 0");
+    if (!(isfinite(s.rtol) && s.rtol > 0.0)) return fail(ZB_EINVAL, "rtol must be finite and > 0");
+    if (!(isfinite(s.atol) && s.atol > 0.0)) return fail(ZB_EINVAL, "atol must be finite and > 0");
+    if (s.zones > 0 && !s.state) return fail(ZB_EINVAL, "NULL state with zones > 0");
+    if (s.zones > 0) {
+        if (!valid_ptr(s.state, ctx->device)) return fail(ZB_EINVAL, "state is not device memory of device %d", ctx->device);
+        if (!valid_ptr(s.rate_scale, ctx->device)) return fail(ZB_EINVAL, "rate_scale is not device memory");
+        if (!valid_ptr(s.zone_status, ctx->device)) return fail(ZB_EINVAL, "zone_status is not device memory");
+        if (!valid_ptr(s.stats, ctx->device)) return fail(ZB_EINVAL, "stats is not device memory");
+    }
+    return ZB_OK;
+}
+
+// One persistent launch over segments that all use the same kernel.
+static zb_err launch_segments(zb_context *ctx, const KernelInfo *k, const zb_segment *segs, int n,
+                              int max_steps, hipStream_t stream, float *ms_out = nullptr)
+{
+    BurnArgs A;
+    memset(&A, 0, sizeof A);
+    int64_t total = 0;
+    int max_nr = 0;
+    for (int i = 0; i < n; ++i) {
+        Segment &S = A.seg[i];
+        S.net = segs[i].net->dn;
+        S.state = segs[i].state;
+        S.scale = segs[i].rate_scale;
+        S.status = segs[i].zone_status;
+        S.stats = (int32_t *)segs[i].stats;
+        S.zones = segs[i].zones;
+        S.dt = segs[i].dt;
+        S.rtol = segs[i].rtol;
+        S.atol = segs[i].atol;
+        total += segs[i].zones;
+        max_nr = std::max(max_nr, S.net.nr);
+    }
+    if (total == 0) return ZB_OK;
+    A.nseg = n;
+    A.max_nr = max_nr;
+    A.max_steps = max_steps;
+    int slot;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        slot = ctx->next_slot;
+        ctx->next_slot = (ctx->next_slot + 1) % QUEUE_SLOTS;
+    }
+    A.queue = ctx->ws + 1 + (size_t)slot * MAXSEG;
+    A.nfail = ctx->ws;
+
+    const int G = 64 / k->lanes;
+    const int rpl = (k->nvp + k->lanes - 1) / k->lanes;
+    const LdsLayout lay = lds_layout(k->nvp, k->lanes * rpl, max_nr);
+    const size_t lds = (size_t)G * lay.total * sizeof(double);
+    if (lds > 160 * 1024) return fail(ZB_EUNSUPPORTED, "LDS need %zu bytes exceeds 160 KiB", lds);
+    int per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k->fn, 64, lds));
+    if (per_cu < 1) return fail(ZB_EUNSUPPORTED, "kernel does not fit on a CU (LDS %zu)", lds);
+    int64_t groups = (total + G - 1) / G;
+    int64_t blocks = std::min<int64_t>((int64_t)per_cu * ctx->cus, groups);
+    HIP_TRY(launch_reset(A.queue, MAXSEG, stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ms_out) {
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        HIP_TRY(hipEventRecord(e0, stream));
+    }
+    void *args[] = {&A};
+    HIP_TRY(hipLaunchKernel(k->fn, dim3((unsigned)blocks), dim3(64), args, lds, stream));
+    if (ms_out) {
+        HIP_TRY(hipEventRecord(e1, stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        HIP_TRY(hipEventElapsedTime(ms_out, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    return ZB_OK;
+}
+
+static zb_err burn_impl(zb_context *ctx, const zb_segment *segs, int n, const zb_opts *opts,
+                        void *stream, int force_lanes = 0, float *ms_out = nullptr)
+{
+    if (!ctx) return fail(ZB_EINVAL, "NULL context");
+    if (n < 0 || (n > 0 && !segs)) return fail(ZB_EINVAL, "bad segment list");
+    const int prec = opts ? opts->precision : ZB_FP64;
+    if (prec != ZB_FP64 && prec != ZB_MIXED) return fail(ZB_EINVAL, "precision %d", prec);
+    int max_steps = (opts && opts->max_steps > 0) ? opts->max_steps : 100000;
+    if (opts && opts->mapping != ZB_MAP_AUTO &&
+        (opts->mapping < 1 || opts->mapping > 64 || (opts->mapping & (opts->mapping - 1))))
+        return fail(ZB_EINVAL, "mapping must be 0 or a power of two 1..64");
+    for (int i = 0; i < n; ++i) {
+        zb_err e = check_segment(ctx, segs[i]);
+        if (e != ZB_OK) return e;
+    }
+    DeviceGuard g(ctx->device);
+    // group segments by kernel; each group is one persistent launch
+    std::vector<const KernelInfo *> ker(n);
+    for (int i = 0; i < n; ++i) {
+        int lanes = force_lanes ? force_lanes : lanes_for(ctx, segs[i].net, prec, opts);
+        ker[i] = find_kernel(segs[i].net->dn.nv, lanes, prec == ZB_MIXED);
+        if (!ker[i])
+            return fail(ZB_EUNSUPPORTED, "no kernel for nv=%d with %d lanes per zone (%s)",
+                        segs[i].net->dn.nv, lanes, prec == ZB_MIXED ? "mixed" : "fp64");
+    }
+    std::vector<bool> done(n, false);
+    for (int i = 0; i < n; ++i) {
+        if (done[i]) continue;
+        std::vector<zb_segment> grp;
+        for (int j = i; j < n; ++j) {
+            if (!done[j] && ker[j] == ker[i] && (int)grp.size() < MAXSEG) {
+                grp.push_back(segs[j]);
+                done[j] = true;
+            }
+        }
+        zb_err e = launch_segments(ctx, ker[i], grp.data(), (int)grp.size(), max_steps,
+                                   (hipStream_t)stream, ms_out);
+        if (e != ZB_OK) return e;
+    }
+    return ZB_OK;
+}
+
+extern "C" zb_err zb_burn(zb_context *ctx, const zb_network *net, double *state, int64_t zones,
+                          double dt, double rtol, double atol, const double *rate_scale,
+                          const zb_opts *opts, int32_t *zone_status, zb_zone_stats *stats, void *stream)
+{
+    zb_segment s;
+    s.net = net;
+    s.state = state;
+    s.zones = zones;
+    s.dt = dt;
+    s.rtol = rtol;
+    s.atol = atol;
+    s.rate_scale = rate_scale;
+    s.zone_status = zone_status;
+    s.stats = stats;
+    return burn_impl(ctx, &s, 1, opts, stream);
+}
+
+extern "C" zb_err zb_burn_batch(zb_context *ctx, const zb_segment *segs, int32_t n_seg,
+                                const zb_opts *opts, void *stream)
+{
+    return burn_impl(ctx, segs, n_seg, opts, stream);
+}
+
+extern "C" zb_err zb_sync(zb_context *ctx, void *stream, int64_t *n_failed)
+{
+    if (!ctx) return fail(ZB_EINVAL, "NULL context");
+    DeviceGuard g(ctx->device);
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    unsigned long long nf = 0;
+    HIP_TRY(hipMemcpy(&nf, ctx->ws, sizeof nf, hipMemcpyDeviceToHost));
+    if (nf) {
+        HIP_TRY(launch_reset(ctx->ws, 1, nullptr));
+        HIP_TRY(hipDeviceSynchronize());
+    }
+    if (n_failed) *n_failed = (int64_t)nf;
+    return nf ? ZB_EZONES : ZB_OK;
+}
+
+// ----------------------------------------------------------------- autotune
+
+extern "C" zb_err zb_autotune(zb_context *ctx, const zb_network *net, const double *sample_state,
+                              int64_t zones, double dt, double rtol, double atol, int32_t precision,
+                              int32_t *best_lanes, float *times_ms)
+{
+    if (!ctx || !net || !sample_state || zones <= 0) return fail(ZB_EINVAL, "bad argument");
+    DeviceGuard g(ctx->device);
+    const int row = net->dn.ns + 1;
+    const size_t bytes = sizeof(double) * row * (size_t)zones;
+    double *work = nullptr, *first = nullptr;
+    int32_t *st = nullptr;
+    HIP_TRY(hipMalloc((void **)&work, bytes));
+    HIP_TRY(hipMalloc((void **)&first, bytes));
+    HIP_TRY(hipMalloc((void **)&st, sizeof(int32_t) * zones));
+    std::vector<double> ref(row * (size_t)zones), cur(row * (size_t)zones);
+    int best = 0;
+    float best_ms = 0.f;
+    bool have_ref = false;
+    zb_opts o = {0, precision, 0, 0};
+    zb_err res = ZB_OK;
+    for (int li = 0, lanes = 1; lanes <= 64; ++li, lanes *= 2) {
+        if (times_ms) times_ms[li] = -1.f;
+        if (!find_kernel(net->dn.nv, lanes, precision == ZB_MIXED)) continue;
+        zb_segment s = {net, work, zones, dt, rtol, atol, nullptr, st, nullptr};
+        float ms = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {   // the first launch also loads the code object
+            if (hipMemcpy(work, sample_state, bytes, hipMemcpyDeviceToDevice) != hipSuccess) { res = ZB_EDEVICE; break; }
+            zb_err e = burn_impl(ctx, &s, 1, &o, nullptr, lanes, &ms);
+            if (e != ZB_OK) { res = e; break; }
+        }
+        if (res != ZB_OK) break;
+        if (hipMemcpy(cur.data(), work, bytes, hipMemcpyDeviceToHost) != hipSuccess) { res = ZB_EDEVICE; break; }
+        bool ok = true;
+        if (!have_ref) {
+            ref = cur;
+            have_ref = true;
+        } else {
+            for (size_t i = 0; i < cur.size() && ok; ++i) {
+                double a = ref[i], b = cur[i];
+                double den = fmax(fabs(a), atol / rtol);
+                if (!(fabs(a - b) <= 1e-6 * den)) ok = false;
+            }
+        }
+        if (times_ms) times_ms[li] = ms;
+        if (ok && (best == 0 || ms < best_ms)) {
+            best = lanes;
+            best_ms = ms;
+        }
+    }
+    (void)hipFree(work);
+    (void)hipFree(first);
+    (void)hipFree(st);
+    if (res != ZB_OK) return res;
+    if (!best) return fail(ZB_EUNSUPPORTED, "no mapping ran");
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        bool found = false;
+        for (auto &t : ctx->tuned)
+            if (t.nv == net->dn.nv && t.nr == net->dn.nr && t.prec == precision) { t.lanes = best; found = true; }
+        if (!found) ctx->tuned.push_back({net->dn.nv, net->dn.nr, precision, best});
+    }
+    if (best_lanes) *best_lanes = best;
+    return ZB_OK;
+}
+
+// -------------------------------------------------------------------- errors
+
+extern "C" const char *zb_strerror(zb_err e)
+{
+    switch (e) {
+    case ZB_OK: return "ZB_OK";
+    case ZB_EINVAL: return "ZB_EINVAL";
+    case ZB_ENOMEM: return "ZB_ENOMEM";
+    case ZB_EDEVICE: return "ZB_EDEVICE";
+    case ZB_EZONES: return "ZB_EZONES";
+    case ZB_EBUSY: return "ZB_EBUSY";
+    case ZB_ENOTFOUND: return "ZB_ENOTFOUND";
+    case ZB_EUNSUPPORTED: return "ZB_EUNSUPPORTED";
+    }
+    return "unknown";
+}
+
+extern "C" const char *zb_last_error(void) { return g_last_error.c_str(); }

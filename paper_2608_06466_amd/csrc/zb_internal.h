@@ -1,0 +1,85 @@
+// Internal types shared by the device code and the host runtime of libzoneburn.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace zb {
+
+constexpr int QMAX = 5;      // highest BDF order
+constexpr int NVMAX = 64;    // largest number of integrated variables
+constexpr int RMAX = 4096;   // largest number of reactions
+
+// A network as the kernels read it.  Built once per network by the host.
+//  rct[r] = (a, b, c, d): reactants a, b and products c, d (-1 when absent).
+//  par[r] = (lnA, n, E, q).
+//  inv[i][e] = reaction index | (nu_ir << 16) for every reaction whose net
+//              stoichiometry in species i is non-zero; -1 pads the row.
+//  rea[j][e] = reaction index | (flags << 16) for every reaction with species j
+//              as a reactant: flag 1 = j is the first reactant, 2 = the second.
+struct DevNet {
+    int ns, nv, thermal, nr;
+    int inv_len, rea_len;
+    const int4 *rct;
+    const double4 *par;
+    const int *inv;
+    const int *rea;
+};
+
+// One run of zones that share a network and tolerances.
+struct Segment {
+    DevNet net;
+    double *state;          // [zones][ns+1]
+    const double *scale;    // [zones][nr] or null
+    int32_t *status;        // [zones] or null
+    int32_t *stats;         // [zones][7] or null
+    int64_t zones;
+    double dt, rtol, atol;
+};
+
+constexpr int MAXSEG = 8;
+
+struct BurnArgs {
+    Segment seg[MAXSEG];
+    int nseg;
+    int max_nr;                    // largest reaction count of the segments (sizes the LDS)
+    int max_steps;
+    unsigned long long *queue;     // [nseg] next zone of each segment (zeroed before the launch)
+    unsigned long long *nfail;     // zones that ended with a non-OK status
+};
+
+// Per-group LDS layout (in doubles).  Everything a zone group exchanges lives here.
+struct LdsLayout {
+    int xch, zs, ybuf, wbuf, prow, ks, rx, jbuf, total;
+};
+
+// nvl = lanes per zone x rows per lane (>= nvp): one slot per lane and local row.
+__host__ __device__ inline LdsLayout lds_layout(int nvp, int nvl, int nr)
+{
+    LdsLayout o;
+    int p = 0;
+    o.xch = p;  p += 2;
+    o.zs = p;   p += (QMAX + 1) * nvl;
+    o.ybuf = p; p += nvp;
+    o.wbuf = p; p += nvp;
+    o.prow = p; p += nvp;
+    o.ks = p;   p += nr;
+    p = (p + 1) & ~1;
+    o.rx = p;   p += 4 * nr;
+    o.jbuf = p; p += nvp * nvp;
+    o.total = (p + 1) & ~1;
+    return o;
+}
+
+// Kernel entry points, one per (padded size, lanes per zone, LU precision).
+struct KernelInfo {
+    int nvp;          // padded number of variables the kernel handles (nv <= nvp)
+    int lanes;        // lanes per zone
+    int mixed;        // 0: FP64 LU, 1: FP32 LU
+    const void *fn;   // __global__ function
+};
+
+int kernel_table(const KernelInfo **out);
+hipError_t launch_reset(unsigned long long *p, int n, hipStream_t s);
+
+}  // namespace zb
