@@ -262,14 +262,18 @@ __device__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const double (&yv)[Zone<
     for (int r = c.gl; r < N.nr; r += L) {
         int4 ix = N.rct[r];
         double4 pr = N.par[r];
-        double Ya = ybuf[ix.x];
-        double Yb = ix.y >= 0 ? ybuf[ix.y] : 1.0;
+        // rates see max(Y, 0); the Jacobian is the derivative of that (1 at Y = 0)
+        const double ya = ybuf[ix.x];
+        const double yb = ix.y >= 0 ? ybuf[ix.y] : 1.0;
+        const double Ya = ya < 0.0 ? 0.0 : ya;
+        const double Yb = yb < 0.0 ? 0.0 : yb;
         double k = ks[r];
         if (N.thermal) k *= exp(pr.x + pr.y * lnT - pr.z * iT);
         double kYb = k * Yb;
         double w = kYb * Ya;
         if (WANTJ) {
-            double kb = ix.y >= 0 ? k * Ya : 0.0;
+            if (ya < 0.0) kYb = 0.0;
+            double kb = (ix.y >= 0 && !(yb < 0.0)) ? k * Ya : 0.0;
             double kt = N.thermal ? w * (pr.y + pr.z * iT) * iT : 0.0;
             double4 *o = (double4 *)(rx + 4 * r);
             *o = make_double4(w, kYb, kb, kt);

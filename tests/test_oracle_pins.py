@@ -247,6 +247,36 @@ def test_rhs_conserves_species_and_energy():
         assert abs(f[-1] + B @ f[:-1]) <= 1e-12 * (abs(f[-1]) + np.abs(B * f[:-1]).sum())
 
 
+def test_rates_see_no_negative_abundance():
+    """A+A->C+D with Y_A slightly negative: dY/dt = -2k Y^2 would run away; the rate law sees
+    max(Y, 0), so nothing reacts and Y_A keeps its round-off value."""
+    net = W.two_body_network(1e15, same=True)
+    y = np.array([-1e-13, 0.0, 0.4, 0.6, 0.0])
+    assert np.all(oracle.rhs(net, y) == 0.0)
+    assert np.all(oracle.jac(net, y) == 0.0)
+    out, status, _ = oracle.burn(net, y[None, :], 1.0, RTOL, ATOL)
+    assert status[0] == 0 and np.array_equal(out[0], y)
+    # at Y = 0 the Jacobian takes the right derivative; a negative partner enters as 0
+    J0 = oracle.jac(W.two_body_network(2.0), np.array([0.0, 0.5, 0.0, 0.0, 0.0]))
+    assert J0[0, 0] == -2.0 * 0.5 and J0[0, 1] == 0.0
+    J1 = oracle.jac(W.two_body_network(2.0), np.array([0.3, -1e-14, 0.0, 0.0, 0.0]))
+    assert J1[0, 0] == 0.0 and J1[0, 1] == 0.0
+
+
+@pytest.mark.slow
+def test_zone_that_once_ran_onto_a_negative_branch():
+    """Config-2 zone 602567: without the max(Y, 0) rate law the burn ended with Y_8 = -0.044."""
+    c = W.config2()
+    y0 = c["state"][602567]
+    net = oracle.Net(c["net"])
+    sol = solve_ivp(lambda t, y: oracle.rhs(net, y), (0, 1.0), y0, method="Radau",
+                    rtol=1e-12, atol=1e-18, jac=lambda t, y: oracle.jac(net, y))
+    out, status, _ = oracle.burn(net, y0[None, :], 1.0, RTOL, ATOL)
+    assert status[0] == 0
+    assert out[0, :13].min() > -1e-12
+    assert gated_err(out[0], sol.y[:, -1]) < 1e-6
+
+
 def test_arrhenius_rate_first_order_decay():
     """A -> B with k = A T^n exp(-E/T) at fixed T (q = 0): Y_A(t) = Y_A(0) exp(-k t)."""
     A, nexp, E, T = 3.0e4, 0.7, 2.0e3, 900.0
