@@ -5,14 +5,15 @@
  * a (and b, if second order) and products c (and d):
  *   k_r = s_r * exp(lnA_r + n_r ln T - E_r / T)        (thermal network)
  *   k_r = s_r * exp(lnA_r)                             (no temperature coupling)
- *   w_r = k_r Y+_a Y+_b   (k_r Y+_a for a first-order reaction; k_r Y+_a^2 when a == b)
- * where Y+ = max(Y, 0): the rates see no negative abundance.  The exact
- * solution never leaves Y >= 0, so this changes nothing there; it keeps a
- * round-off excursion below zero from feeding the unstable branch of a
- * quadratic self-reaction (dY/dt = -2k Y^2 runs away for Y < 0).  The state
- * itself is never clipped, so the linear invariants of the network hold.
- * The Jacobian is the exact derivative of this right-hand side, taking the
- * right derivative (1) of Y+ at Y = 0.
+ *   w_r = s_r k_r Y_a Y_b (k_r Y_a for a first-order reaction), where the sign
+ *         s_r = -1 when both reactants are negative and +1 otherwise; for
+ *         A + A this is k Y_A |Y_A|.
+ * The exact solution never leaves Y >= 0, where s_r = 1 and this is plain mass
+ * action.  Off that set the sign makes a negative abundance be pulled back to
+ * zero, as one negative reactant with a positive partner already is, instead
+ * of running away: with s_r = 1 a quadratic self-reaction gives dY/dt = -2k Y^2,
+ * which diverges for Y < 0.  w stays continuous, and for A + A continuously
+ * differentiable; mass is conserved exactly.
  *   dY_i/dt = sum_r nu_ir w_r,   nu_ir = #(i among products) - #(i among reactants)
  *   dT/dt   = sum_r q_r w_r      (thermal network only)
  * The Jacobian is the exact derivative of this right-hand side.
@@ -21,11 +22,6 @@
 #include <string.h>
 
 #include "oracle.h"
-
-/* Y+ = max(Y, 0), written so that a NaN stays a NaN; and its derivative (1 at Y = 0). */
-static double pos(double y) { return y < 0.0 ? 0.0 : y; }
-static double dpos(double y) { return y < 0.0 ? 0.0 : 1.0; }
-static double complex cpos(double complex y) { return creal(y) < 0.0 ? 0.0 : y; }
 
 int orc_nvar(const orc_net *net) { return net->ns + (net->thermal ? 1 : 0); }
 
@@ -66,8 +62,8 @@ void orc_rhs(const orc_net *net, const double *scale, const double *y, double *f
     for (int r = 0; r < net->nr; r++) {
         int a = net->reactant[2 * r], b = net->reactant[2 * r + 1];
         int c = net->product[2 * r], d = net->product[2 * r + 1];
-        double w = k[r] * pos(y[a]);
-        if (b >= 0) w *= pos(y[b]);
+        double w = k[r] * y[a];
+        if (b >= 0) w *= (y[a] < 0.0 && y[b] < 0.0) ? -y[b] : y[b];
         f[a] -= w;
         if (b >= 0) f[b] -= w;
         f[c] += w;
@@ -92,8 +88,8 @@ void orc_rhs_cplx(const orc_net *net, const double *scale, const double complex 
         }
         int a = net->reactant[2 * r], b = net->reactant[2 * r + 1];
         int c = net->product[2 * r], d = net->product[2 * r + 1];
-        double complex w = kr * cpos(y[a]);
-        if (b >= 0) w *= cpos(y[b]);
+        double complex w = kr * y[a];
+        if (b >= 0) w *= (creal(y[a]) < 0.0 && creal(y[b]) < 0.0) ? -y[b] : y[b];
         f[a] -= w;
         if (b >= 0) f[b] -= w;
         f[c] += w;
@@ -114,12 +110,13 @@ void orc_jac(const orc_net *net, const double *scale, const double *y, double *J
         /* partial derivatives of w_r */
         double dwa, dwb = 0.0, dwT = 0.0;
         if (b >= 0) {
-            dwa = k[r] * pos(y[b]) * dpos(y[a]);
-            dwb = k[r] * pos(y[a]) * dpos(y[b]);
-            if (net->thermal) dwT = dk[r] * pos(y[a]) * pos(y[b]);
+            double sg = (y[a] < 0.0 && y[b] < 0.0) ? -1.0 : 1.0;
+            dwa = sg * k[r] * y[b];
+            dwb = sg * k[r] * y[a];
+            if (net->thermal) dwT = sg * dk[r] * y[a] * y[b];
         } else {
-            dwa = k[r] * dpos(y[a]);
-            if (net->thermal) dwT = dk[r] * pos(y[a]);
+            dwa = k[r];
+            if (net->thermal) dwT = dk[r] * y[a];
         }
         /* rows touched by reaction r and their stoichiometric weights */
         int rows[5];

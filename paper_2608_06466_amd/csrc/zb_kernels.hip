@@ -262,18 +262,17 @@ __device__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const double (&yv)[Zone<
     for (int r = c.gl; r < N.nr; r += L) {
         int4 ix = N.rct[r];
         double4 pr = N.par[r];
-        // rates see max(Y, 0); the Jacobian is the derivative of that (1 at Y = 0)
+        // sign-aware mass action: w = s k Ya Yb with s = -1 when both reactants are
+        // negative (k Ya |Ya| for A + A), so a negative abundance is pulled back to 0
         const double ya = ybuf[ix.x];
-        const double yb = ix.y >= 0 ? ybuf[ix.y] : 1.0;
-        const double Ya = ya < 0.0 ? 0.0 : ya;
-        const double Yb = yb < 0.0 ? 0.0 : yb;
+        const double yb0 = ix.y >= 0 ? ybuf[ix.y] : 1.0;
+        const double yb = (ya < 0.0 && yb0 < 0.0) ? -yb0 : yb0;
         double k = ks[r];
         if (N.thermal) k *= exp(pr.x + pr.y * lnT - pr.z * iT);
-        double kYb = k * Yb;
-        double w = kYb * Ya;
+        double kYb = k * yb;
+        double w = kYb * ya;
         if (WANTJ) {
-            if (ya < 0.0) kYb = 0.0;
-            double kb = (ix.y >= 0 && !(yb < 0.0)) ? k * Ya : 0.0;
+            double kb = ix.y >= 0 ? ((ya < 0.0 && yb0 < 0.0) ? -k * ya : k * ya) : 0.0;
             double kt = N.thermal ? w * (pr.y + pr.z * iT) * iT : 0.0;
             double4 *o = (double4 *)(rx + 4 * r);
             *o = make_double4(w, kYb, kb, kt);

@@ -247,25 +247,43 @@ def test_rhs_conserves_species_and_energy():
         assert abs(f[-1] + B @ f[:-1]) <= 1e-12 * (abs(f[-1]) + np.abs(B * f[:-1]).sum())
 
 
-def test_rates_see_no_negative_abundance():
-    """A+A->C+D with Y_A slightly negative: dY/dt = -2k Y^2 would run away; the rate law sees
-    max(Y, 0), so nothing reacts and Y_A keeps its round-off value."""
+def test_negative_abundance_is_pulled_back():
+    """A+A->C+D, k = 1e15, from Y_A = -1e-13.  Plain mass action gives dY/dt = -2k Y^2 < 0 and
+    runs away within ~1/(2k|Y|) = 5e-3; the sign-aware rate k Y|Y| pulls Y_A back to zero."""
     net = W.two_body_network(1e15, same=True)
     y = np.array([-1e-13, 0.0, 0.4, 0.6, 0.0])
-    assert np.all(oracle.rhs(net, y) == 0.0)
-    assert np.all(oracle.jac(net, y) == 0.0)
+    f = oracle.rhs(net, y)
+    assert f[0] > 0.0 and f[2] < 0.0 and abs(f.sum()) < 1e-25
     out, status, _ = oracle.burn(net, y[None, :], 1.0, RTOL, ATOL)
-    assert status[0] == 0 and np.array_equal(out[0], y)
-    # at Y = 0 the Jacobian takes the right derivative; a negative partner enters as 0
-    J0 = oracle.jac(W.two_body_network(2.0), np.array([0.0, 0.5, 0.0, 0.0, 0.0]))
-    assert J0[0, 0] == -2.0 * 0.5 and J0[0, 1] == 0.0
-    J1 = oracle.jac(W.two_body_network(2.0), np.array([0.3, -1e-14, 0.0, 0.0, 0.0]))
-    assert J1[0, 0] == 0.0 and J1[0, 1] == 0.0
+    assert status[0] == 0 and abs(out[0, 0]) < 1e-13
+    assert abs(out[0, 2] - 0.4) < 1e-13 and abs(out[0, :4].sum() - y[:4].sum()) < 1e-15
+    # one negative reactant with a positive partner: plain mass action (already restoring)
+    n2 = W.two_body_network(3.0)
+    y2 = np.array([-1e-12, 0.5, 0.1, 0.1, 0.0])
+    assert oracle.rhs(n2, y2)[0] == pytest.approx(-3.0 * (-1e-12 * 0.5), rel=1e-14)
+    # both negative: the sign flips
+    y3 = np.array([-1e-12, -2e-12, 0.1, 0.1, 0.0])
+    assert oracle.rhs(n2, y3)[0] == pytest.approx(-3.0 * (-(-1e-12 * -2e-12)), rel=1e-14)
+
+
+def test_jacobian_complex_step_with_negative_abundances():
+    net = W.config2_network()
+    y = W.random_zones(net, 1, seed=12)[0]
+    y[[1, 4, 7]] = [-3e-13, -1e-12, -2e-14]
+    n = oracle.Net(net)
+    J = oracle.jac(n, y)
+    Jcs = np.zeros_like(J)
+    for j in range(n.nv):
+        h = 1e-30 * max(1.0, abs(y[j]))
+        yc = y.astype(complex)
+        yc[j] += 1j * h
+        Jcs[:, j] = oracle.rhs_complex(n, yc).imag / h
+    np.testing.assert_allclose(J, Jcs, rtol=1e-12, atol=1e-14 * np.abs(J).max())
 
 
 @pytest.mark.slow
 def test_zone_that_once_ran_onto_a_negative_branch():
-    """Config-2 zone 602567: without the max(Y, 0) rate law the burn ended with Y_8 = -0.044."""
+    """Config-2 zone 602567: with plain mass action the burn ended with Y_8 = -0.044."""
     c = W.config2()
     y0 = c["state"][602567]
     net = oracle.Net(c["net"])
