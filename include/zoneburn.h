@@ -131,11 +131,13 @@ zb_err zb_burn_batch(zb_context *ctx, const zb_segment *segs, int32_t n_seg, con
 
 /* Lanes per zone the library uses for (network, precision) when opts->mapping is AUTO. */
 zb_err zb_get_mapping(zb_context *ctx, const zb_network *net, int32_t precision, int32_t *lanes);
-/* Time every supported mapping on a DEVICE sample state [zones][ns+1] (copied, not modified),
-   keep the fastest whose results agree with the first candidate's, and use it from now on.
-   Results are cached per (network size, reactions, precision, device) in the file named by
-   ZB_AUTOTUNE_CACHE, if set.  times_ms (HOST, optional) receives one entry per lane count
-   1,2,4,...,64 (negative when unsupported). */
+/* Time every supported mapping on a DEVICE sample state [zones][ns+1] (copied, not modified)
+   and use the fastest qualifying one for (network size, reactions, precision) on this context
+   from now on.  A mapping qualifies when every sample zone ends with the status the first
+   mapping gave it and at least 99% of the zones agree with that mapping to a gated relative
+   1e-6 (the mappings differ only in the order of reductions).  times_ms (HOST, optional)
+   receives one entry per lane count 1,2,4,...,64 (negative when unsupported).  Allocates
+   device scratch for one copy of the sample; synchronous. */
 zb_err zb_autotune(zb_context *ctx, const zb_network *net, const double *sample_state,
                    int64_t zones, double dt, double rtol, double atol, int32_t precision,
                    int32_t *best_lanes, float *times_ms);

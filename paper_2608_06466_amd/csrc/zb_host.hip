@@ -446,12 +446,12 @@ extern "C" zb_err zb_autotune(zb_context *ctx, const zb_network *net, const doub
     DeviceGuard g(ctx->device);
     const int row = net->dn.ns + 1;
     const size_t bytes = sizeof(double) * row * (size_t)zones;
-    double *work = nullptr, *first = nullptr;
+    double *work = nullptr;
     int32_t *st = nullptr;
     HIP_TRY(hipMalloc((void **)&work, bytes));
-    HIP_TRY(hipMalloc((void **)&first, bytes));
     HIP_TRY(hipMalloc((void **)&st, sizeof(int32_t) * zones));
     std::vector<double> ref(row * (size_t)zones), cur(row * (size_t)zones);
+    std::vector<int32_t> ref_st(zones), cur_st(zones);
     int best = 0;
     float best_ms = 0.f;
     bool have_ref = false;
@@ -468,17 +468,34 @@ extern "C" zb_err zb_autotune(zb_context *ctx, const zb_network *net, const doub
             if (e != ZB_OK) { res = e; break; }
         }
         if (res != ZB_OK) break;
-        if (hipMemcpy(cur.data(), work, bytes, hipMemcpyDeviceToHost) != hipSuccess) { res = ZB_EDEVICE; break; }
+        if (hipMemcpy(cur.data(), work, bytes, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(cur_st.data(), st, sizeof(int32_t) * zones, hipMemcpyDeviceToHost) != hipSuccess) {
+            res = ZB_EDEVICE;
+            break;
+        }
+        // Every mapping runs the same integrator; only the order of the group
+        // reductions differs, so results agree to rounding except on the rare
+        // ill-conditioned zone.  A mapping qualifies when every zone ends with
+        // the status of the first mapping tried and at least 99% of the zones
+        // agree with it to a gated relative 1e-6.
         bool ok = true;
         if (!have_ref) {
-            ref = cur;
+            ref.swap(cur);
+            ref_st.swap(cur_st);
             have_ref = true;
         } else {
-            for (size_t i = 0; i < cur.size() && ok; ++i) {
-                double a = ref[i], b = cur[i];
-                double den = fmax(fabs(a), atol / rtol);
-                if (!(fabs(a - b) <= 1e-6 * den)) ok = false;
+            int64_t agree = 0;
+            for (int64_t z = 0; z < zones && ok; ++z) {
+                if (cur_st[z] != ref_st[z]) ok = false;
+                bool zok = true;
+                for (int i = 0; i < row; ++i) {
+                    double a = ref[z * row + i], b = cur[z * row + i];
+                    double den = fmax(fabs(a), atol / rtol);
+                    if (!(fabs(a - b) <= 1e-6 * den)) zok = false;
+                }
+                agree += zok;
             }
+            if (ok && agree * 100 < zones * 99) ok = false;
         }
         if (times_ms) times_ms[li] = ms;
         if (ok && (best == 0 || ms < best_ms)) {
@@ -487,7 +504,6 @@ extern "C" zb_err zb_autotune(zb_context *ctx, const zb_network *net, const doub
         }
     }
     (void)hipFree(work);
-    (void)hipFree(first);
     (void)hipFree(st);
     if (res != ZB_OK) return res;
     if (!best) return fail(ZB_EUNSUPPORTED, "no mapping ran");

@@ -65,8 +65,8 @@ __host__ __device__ inline LdsLayout lds_layout(int nvp, int nvl, int nr)
     o.prow = p; p += nvp;
     o.ks = p;   p += nr;
     p = (p + 1) & ~1;
-    o.rx = p;   p += 4 * nr;
-    o.jbuf = p; p += nvp * nvp;
+    o.rx = p;   p += 4 * nr;          // w, dw/dYa, dw/dYb, dw/dT: four columns of nr
+    o.jbuf = p; p += nvp * (nvp + 1); // Jacobian rows with an odd stride (no bank conflicts)
     o.total = (p + 1) & ~1;
     return o;
 }

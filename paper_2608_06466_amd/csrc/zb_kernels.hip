@@ -25,6 +25,9 @@
 #include <float.h>
 #include <math.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "zb_internal.h"
 #include "zoneburn.h"
 
@@ -78,6 +81,21 @@ __device__ __forceinline__ T xor_lane(T v, int m)
     return __shfl_xor(v, m, 64);
 }
 
+// Compile-time loop: f(std::integral_constant<int, i>) for i = B .. E-1.  Indices of
+// register arrays stay constant expressions even where a loop bound depends on an
+// outer index, which ordinary unrolling does not guarantee.
+template <int B, class F, int... I>
+__device__ __forceinline__ void sfor_impl(F &&f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, B + I>{}), ...);
+}
+
+template <int B, int E, class F>
+__device__ __forceinline__ void sfor(F &&f)
+{
+    if constexpr (E > B) sfor_impl<B>(f, std::make_integer_sequence<int, E - B>{});
+}
+
 struct OpAdd { template <class T> __device__ T operator()(T a, T b) const { return a + b; } };
 struct OpMax { template <class T> __device__ T operator()(T a, T b) const { return a > b ? a : b; } };
 struct OpMin { template <class T> __device__ T operator()(T a, T b) const { return a < b ? a : b; } };
@@ -100,6 +118,31 @@ template <int L, class T>
 __device__ __forceinline__ T gbcast(T v, bool owner)
 {
     return greduce<L>(owner ? v : T(0), OpAdd());
+}
+
+// Same, through a group LDS slot: one store by the owner, one load by everyone.
+template <int L, class T>
+__device__ __forceinline__ T gbcast_lds(T v, bool owner, double *slot)
+{
+    if constexpr (L == 1) return v;
+    if (owner) *slot = (double)v;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    T r = (T)*slot;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    return r;
+}
+
+#ifndef ZB_SOLVE_LDS
+#define ZB_SOLVE_LDS 0
+#endif
+template <int L, class T>
+__device__ __forceinline__ T gbcast_solve(T v, bool owner, double *slot)
+{
+    if constexpr (ZB_SOLVE_LDS) return gbcast_lds<L>(v, owner, slot);
+    else return gbcast<L>(v, owner);
 }
 
 template <int L>
@@ -151,6 +194,19 @@ __device__ __forceinline__ double stirling(int n, int j)
 #pragma unroll
     for (int r = 1; r < 5; ++r)
         if (n == r + 2) v = t[r][j];
+    return v;
+}
+
+// (2/3 - 1e-6)^n for n = 1..6
+__device__ __forceinline__ double cpow23(int n)
+{
+    const double c = 2.0 / 3.0 - 1e-6;
+    double v = c;
+    v = (n >= 2) ? v * c : v;
+    v = (n >= 3) ? v * c : v;
+    v = (n >= 4) ? v * c : v;
+    v = (n >= 5) ? v * c : v;
+    v = (n >= 6) ? v * c : v;
     return v;
 }
 
@@ -238,17 +294,14 @@ __device__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const double (&yv)[Zone<
         int i = row_of<NVP, L>(c, s);
         if (i < N.nv) ybuf[i] = yv[s];
     }
+    constexpr int JS = NVP + 1;   // Jacobian row stride in LDS
+    const int nr = N.nr;
     if (WANTJ) {
         // clear the Jacobian rows this lane owns (the T row is fully overwritten)
-#pragma unroll
-        for (int s = 0; s < RPL; ++s) {
-            int i = row_of<NVP, L>(c, s);
-            if (i < N.ns) {
-                double2 *r2 = (double2 *)(jb + i * NVP);
-#pragma unroll
-                for (int j = 0; j < NVP / 2; ++j) r2[j] = make_double2(0.0, 0.0);
-            }
-        }
+        sfor<0, RPL>([&](auto S) {
+            int i = row_of<NVP, L>(c, S);
+            if (i < N.ns) sfor<0, NVP>([&](auto J) { jb[i * JS + J] = 0.0; });
+        });
     }
     lds_fence();
 
@@ -271,14 +324,14 @@ __device__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const double (&yv)[Zone<
         if (N.thermal) k *= exp(pr.x + pr.y * lnT - pr.z * iT);
         double kYb = k * yb;
         double w = kYb * ya;
+        rx[r] = w;
         if (WANTJ) {
             double kb = ix.y >= 0 ? ((ya < 0.0 && yb0 < 0.0) ? -k * ya : k * ya) : 0.0;
             double kt = N.thermal ? w * (pr.y + pr.z * iT) * iT : 0.0;
-            double4 *o = (double4 *)(rx + 4 * r);
-            *o = make_double4(w, kYb, kb, kt);
+            rx[nr + r] = kYb;
+            rx[2 * nr + r] = kb;
+            rx[3 * nr + r] = kt;
             sTT += pr.w * kt;
-        } else {
-            rx[4 * r] = w;
         }
         sT += pr.w * w;
     }
@@ -296,24 +349,21 @@ __device__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const double (&yv)[Zone<
         if (i < N.ns) {
             const int *lst = N.inv + i * N.inv_len;
             double jit = 0.0;
-            double *jrow = jb + i * NVP;
+            double *jrow = jb + i * JS;
             for (int e = 0; e < N.inv_len; ++e) {
                 int en = lst[e];
                 if (en < 0) break;
                 int r = en & 0xffff;
                 double nu = (double)((en >> 16) - 8);
+                fi = fma(nu, rx[r], fi);
                 if (WANTJ) {
-                    double4 v = *(const double4 *)(rx + 4 * r);
                     int2 ab = *(const int2 *)&N.rct[r];
-                    fi = fma(nu, v.x, fi);
-                    __hip_atomic_fetch_add(jrow + ab.x, nu * v.y, __ATOMIC_RELAXED,
+                    __hip_atomic_fetch_add(jrow + ab.x, nu * rx[nr + r], __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
                     if (ab.y >= 0)
-                        __hip_atomic_fetch_add(jrow + ab.y, nu * v.z, __ATOMIC_RELAXED,
+                        __hip_atomic_fetch_add(jrow + ab.y, nu * rx[2 * nr + r], __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_WORKGROUP);
-                    jit = fma(nu, v.w, jit);
-                } else {
-                    fi = fma(nu, rx[4 * r], fi);
+                    jit = fma(nu, rx[3 * nr + r], jit);
                 }
             }
             if (WANTJ && N.thermal) {
@@ -325,14 +375,14 @@ __device__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const double (&yv)[Zone<
                     if (en < 0) break;
                     int r = en & 0xffff;
                     int fl = en >> 16;
-                    double d = ((fl & 1) ? rx[4 * r + 1] : 0.0) + ((fl & 2) ? rx[4 * r + 2] : 0.0);
+                    double d = ((fl & 1) ? rx[nr + r] : 0.0) + ((fl & 2) ? rx[2 * nr + r] : 0.0);
                     v = fma(N.par[r].w, d, v);
                 }
-                jb[N.ns * NVP + i] = v;
+                jb[N.ns * JS + i] = v;
             }
         } else if (N.thermal && i == N.ns) {
             fi = fT;
-            if (WANTJ) jb[N.ns * NVP + N.ns] = JTT;
+            if (WANTJ) jb[N.ns * JS + N.ns] = JTT;
         }
         fo[s] = fi;
     }
@@ -341,44 +391,32 @@ __device__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const double (&yv)[Zone<
         lds_fence();
         constexpr bool MIXED = sizeof(LT) == 4;
         const double *wb = c.S + c.lay.wbuf;
-#pragma unroll
-        for (int s = 0; s < RPL; ++s) {
-            int i = row_of<NVP, L>(c, s);
+        sfor<0, RPL>([&](auto S) {
+            int i = row_of<NVP, L>(c, S);
             double rmax = 0.0;
             double mrow[NVP];
             if (i < N.nv) {
-                const double2 *r2 = (const double2 *)(jb + i * NVP);
-#pragma unroll
-                for (int j2 = 0; j2 < NVP / 2; ++j2) {
-                    double2 v = r2[j2];
-                    mrow[2 * j2] = v.x;
-                    mrow[2 * j2 + 1] = v.y;
-                }
-#pragma unroll
-                for (int j = 0; j < NVP; ++j) {
-                    double m = (j == i ? 1.0 : 0.0) - gamma * mrow[j];
-                    if (j >= N.nv) m = (j == i) ? 1.0 : 0.0;
+                sfor<0, NVP>([&](auto J) {
+                    double m = (J == i ? 1.0 : 0.0) - gamma * jb[i * JS + J];
+                    if (J >= N.nv) m = (J == i) ? 1.0 : 0.0;
                     if (MIXED) {
-                        m *= wb[j];
+                        m *= wb[J];
                         rmax = fmax(rmax, fabs(m));
                     }
-                    mrow[j] = m;
-                }
+                    mrow[J] = m;
+                });
             } else {
-#pragma unroll
-                for (int j = 0; j < NVP; ++j) mrow[j] = (j == i) ? 1.0 : 0.0;
+                sfor<0, NVP>([&](auto J) { mrow[J] = (J == i) ? 1.0 : 0.0; });
                 rmax = 1.0;
             }
             if (MIXED) {
                 double sc = rmax > 0.0 ? 1.0 / rmax : 1.0;
-                z.rs[s] = (LT)sc;
-#pragma unroll
-                for (int j = 0; j < NVP; ++j) z.M[s][j] = (LT)(mrow[j] * sc);
+                z.rs[S] = (LT)sc;
+                sfor<0, NVP>([&](auto J) { z.M[S][J] = (LT)(mrow[J] * sc); });
             } else {
-#pragma unroll
-                for (int j = 0; j < NVP; ++j) z.M[s][j] = (LT)mrow[j];
+                sfor<0, NVP>([&](auto J) { z.M[S][J] = (LT)mrow[J]; });
             }
-        }
+        });
     }
 }
 
@@ -390,55 +428,49 @@ __device__ void lu_factor(const Ctx &c, Zone<NVP, L, LT> &z)
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
     LT *prow = (LT *)(c.S + c.lay.prow);
     const int nv = c.net.nv;
-#pragma unroll
-    for (int s = 0; s < RPL; ++s) z.pstep[s] = 127;
-#pragma unroll
-    for (int k = 0; k < NVP; ++k) {
-        if (k >= nv) continue;   // (no early exit: the loop must unroll fully)
+    sfor<0, RPL>([&](auto S) { z.pstep[S] = 127; });
+    sfor<0, NVP>([&](auto K) {
+        constexpr int k = K;
+        if (k >= nv) return;
         double bv = -1.0;
         int bi = 1 << 20;
-#pragma unroll
-        for (int s = 0; s < RPL; ++s) {
-            int i = row_of<NVP, L>(c, s);
-            double a = fabs((double)z.M[s][k]);
-            if (z.pstep[s] > k && i < nv && a > bv) {
+        sfor<0, RPL>([&](auto S) {
+            int i = row_of<NVP, L>(c, S);
+            double a = fabs((double)z.M[S][k]);
+            if (z.pstep[S] > k && i < nv && a > bv) {
                 bv = a;
                 bi = i;
             }
-        }
+        });
         double gm = greduce<L>(bv, OpMax());
         int p = greduce<L>(bv == gm ? bi : (1 << 20), OpMin());
         int pl = p & (L - 1);
         int ps = p / L;
         if (c.gl == pl) {
-#pragma unroll
-            for (int j = k; j < NVP; ++j) {
-                LT v = opq(z.M[0][j]);
-#pragma unroll
-                for (int s = 1; s < RPL; ++s) {
-                    LT cand = opq(z.M[s][j]);
-                    v = (ps == s) ? cand : v;
-                }
-                prow[j] = v;
-            }
+            sfor<k, NVP>([&](auto J) {
+                LT v = opq(z.M[0][J]);
+                sfor<1, RPL>([&](auto S) {
+                    LT cand = opq(z.M[S][J]);
+                    v = (ps == S) ? cand : v;
+                });
+                prow[J] = v;
+            });
         }
         lds_fence();
         LT rinv = LT(1) / prow[k];
-#pragma unroll
-        for (int s = 0; s < RPL; ++s) {
-            int i = row_of<NVP, L>(c, s);
+        sfor<0, RPL>([&](auto S) {
+            int i = row_of<NVP, L>(c, S);
             if (i == p) {
-                z.pstep[s] = k;
-                z.dinv[s] = rinv;
+                z.pstep[S] = k;
+                z.dinv[S] = rinv;
             }
-            bool act = z.pstep[s] > k;
-            LT l = act ? z.M[s][k] * rinv : LT(0);
-            if (act) z.M[s][k] = l;
-#pragma unroll
-            for (int j = k + 1; j < NVP; ++j) z.M[s][j] = fma(-l, prow[j], z.M[s][j]);
-        }
+            bool act = z.pstep[S] > k;
+            LT l = act ? z.M[S][k] * rinv : LT(0);
+            if (act) z.M[S][k] = l;
+            sfor<k + 1, NVP>([&](auto J) { z.M[S][J] = fma(-l, prow[J], z.M[S][J]); });
+        });
         lds_fence();
-    }
+    });
 }
 
 // Solve M x = b: b by local row in, x by local component out (same slots).
@@ -449,52 +481,48 @@ __device__ void lu_solve(const Ctx &c, const Zone<NVP, L, LT> &z, double (&b)[Zo
     constexpr bool MIXED = sizeof(LT) == 4;
     const int nv = c.net.nv;
     LT bb[RPL], x[RPL];
-#pragma unroll
-    for (int s = 0; s < RPL; ++s) {
-        bb[s] = MIXED ? (LT)(b[s] * (double)z.rs[s]) : (LT)b[s];
-        x[s] = LT(0);
-    }
-#pragma unroll
-    for (int k = 0; k < NVP; ++k) {
-        if (k >= nv) continue;
+    sfor<0, RPL>([&](auto S) {
+        bb[S] = MIXED ? (LT)(b[S] * (double)z.rs[S]) : (LT)b[S];
+        x[S] = LT(0);
+    });
+    sfor<0, NVP>([&](auto K) {
+        constexpr int k = K;
+        if (k >= nv) return;
         LT v = LT(0);
         bool own = false;
-#pragma unroll
-        for (int s = 0; s < RPL; ++s) {
-            LT cand = opq(bb[s]);
-            if (z.pstep[s] == k) { v = cand; own = true; }
-        }
-        LT zk = gbcast<L>(v, own);
-#pragma unroll
-        for (int s = 0; s < RPL; ++s)
-            if (z.pstep[s] > k) bb[s] = fma(-z.M[s][k], zk, bb[s]);
-    }
-#pragma unroll
-    for (int k = NVP - 1; k >= 0; --k) {
-        if (k >= nv) continue;
+        sfor<0, RPL>([&](auto S) {
+            LT cand = opq(bb[S]);
+            if (z.pstep[S] == k) { v = cand; own = true; }
+        });
+        LT zk = gbcast_solve<L>(v, own, c.S + c.lay.xch);
+        sfor<0, RPL>([&](auto S) {
+            if (z.pstep[S] > k) bb[S] = fma(-z.M[S][k], zk, bb[S]);
+        });
+    });
+    sfor<0, NVP>([&](auto KK) {
+        constexpr int k = NVP - 1 - KK;
+        if (k >= nv) return;
         LT v = LT(0);
         bool own = false;
-#pragma unroll
-        for (int s = 0; s < RPL; ++s) {
-            LT cand = opq(bb[s]) * opq(z.dinv[s]);
-            if (z.pstep[s] == k) { v = cand; own = true; }
-        }
-        LT xk = gbcast<L>(v, own);
-#pragma unroll
-        for (int s = 0; s < RPL; ++s)
-            if (z.pstep[s] < k) bb[s] = fma(-z.M[s][k], xk, bb[s]);
+        sfor<0, RPL>([&](auto S) {
+            LT cand = opq(bb[S]) * opq(z.dinv[S]);
+            if (z.pstep[S] == k) { v = cand; own = true; }
+        });
+        LT xk = gbcast_solve<L>(v, own, c.S + c.lay.xch);
+        sfor<0, RPL>([&](auto S) {
+            if (z.pstep[S] < k) bb[S] = fma(-z.M[S][k], xk, bb[S]);
+        });
         if (c.gl == (k % L)) x[k / L] = xk;
-    }
+    });
     const double *wb = c.S + c.lay.wbuf;
-#pragma unroll
-    for (int s = 0; s < RPL; ++s) {
-        double v = (double)x[s];
+    sfor<0, RPL>([&](auto S) {
+        double v = (double)x[S];
         if (MIXED) {
-            int i = row_of<NVP, L>(c, s);
+            int i = row_of<NVP, L>(c, S);
             if (i < NVP) v *= wb[i];
         }
-        b[s] = v;
-    }
+        b[S] = v;
+    });
 }
 
 // ------------------------------------------------------------ integrator
@@ -740,8 +768,12 @@ __device__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z, int max_steps)
 
     if (z.nequal >= z.q + 1) {
         const int q = z.q;
-        double best = 1.0 / (pow(6.0 * err, 1.0 / (double)(q + 1)) + 1e-6);
-        int qnew = q;
+        // eta_p = 1 / ((b E_p)^(1/(p+1)) + 1e-6) >= 1.5  iff  b E_p <= (2/3 - 1e-6)^(p+1).
+        // The powers are evaluated only when some order may pass (a conservative
+        // pre-filter, so every decision is the one the plain formula gives).
+        const double cq = cpow23(q + 1) * (1.0 + 1e-9);
+        bool may = 6.0 * err <= cq;
+        double Em = 0.0, Ep = 0.0;
         if (q > 1) {
             double zq[RPL];
 #pragma unroll
@@ -754,15 +786,24 @@ __device__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z, int max_steps)
                 }
                 zq[s] = v;
             }
-            double Em = factorial(q - 1) * wrms(c, z, zq);
-            double etam = 1.0 / (pow(6.0 * Em, 1.0 / (double)q) + 1e-6);
-            if (etam > best) { best = etam; qnew = q - 1; }
+            Em = factorial(q - 1) * wrms(c, z, zq);
+            may = may || (6.0 * Em <= cpow23(q) * (1.0 + 1e-9));
         }
         if (q < QMAX) {
             double dd[RPL];
 #pragma unroll
             for (int s = 0; s < RPL; ++s) dd[s] = z.dy[s] - z.dyp[s];
-            double Ep = wrms(c, z, dd) / (double)(q + 2);
+            Ep = wrms(c, z, dd) / (double)(q + 2);
+            may = may || (10.0 * Ep <= cpow23(q + 2) * (1.0 + 1e-9));
+        }
+        double best = 0.0;
+        int qnew = q;
+        if (may) best = 1.0 / (pow(6.0 * err, 1.0 / (double)(q + 1)) + 1e-6);
+        if (may && q > 1) {
+            double etam = 1.0 / (pow(6.0 * Em, 1.0 / (double)q) + 1e-6);
+            if (etam > best) { best = etam; qnew = q - 1; }
+        }
+        if (may && q < QMAX) {
             double etap = 1.0 / (pow(10.0 * Ep, 1.0 / (double)(q + 2)) + 1e-6);
             if (etap > best) { best = etap; qnew = q + 1; }
         }
@@ -881,8 +922,15 @@ __device__ __forceinline__ void load_segment(Ctx &c, const BurnArgs &A, int seg,
 // Persistent kernel.  Each wave works through the segments in order; within a
 // segment every group of L lanes pulls zones from the segment's queue until it
 // is empty, and the wave moves on once all its groups have found it empty.
+#ifndef ZB_WAVES_PER_EU
+#define ZB_WAVES_PER_EU 0
+#endif
 template <int NVP, int L, class LT>
-__global__ __launch_bounds__(64) void burn_kernel(BurnArgs A)
+__global__ __launch_bounds__(64)
+#if ZB_WAVES_PER_EU > 0
+__attribute__((amdgpu_waves_per_eu(ZB_WAVES_PER_EU)))
+#endif
+void burn_kernel(BurnArgs A)
 {
     extern __shared__ double smem[];
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
@@ -952,6 +1000,8 @@ static const KernelInfo g_kernels[] = {
     ZB_K(4, 1, double, 0),   ZB_K(4, 4, double, 0),   ZB_K(4, 1, float, 1),  ZB_K(4, 4, float, 1),
     ZB_K(8, 8, double, 0),   ZB_K(8, 8, float, 1),
     ZB_K(16, 16, double, 0), ZB_K(16, 16, float, 1),
+    ZB_K(16, 8, double, 0),  ZB_K(16, 8, float, 1),
+    ZB_K(16, 4, double, 0),  ZB_K(16, 4, float, 1),
     ZB_K(24, 32, double, 0), ZB_K(24, 32, float, 1),
     ZB_K(32, 32, double, 0), ZB_K(32, 32, float, 1),
     ZB_K(48, 64, double, 0), ZB_K(48, 64, float, 1),

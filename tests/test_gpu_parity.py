@@ -278,3 +278,30 @@ def test_parity_tail_on_thousands_of_zones(zbm, which):
         gpu, fine = run_pair(zb, ctx, net_d, st, 1.0, 1e-8, 1e-12, precision=prec, net=net)
         check(f"{which} {prec} x{n}", gpu, ref, 1e-8, 1e-12, net_d["n_species"] + 1, fine)
     net.close()
+
+
+def test_autotune_picks_the_fastest_qualifying_mapping(zbm):
+    """zb_autotune times each mapping, and the chosen one then serves AUTO launches."""
+    zb, ctx = zbm
+    c = W.config2(8192)
+    net = zb.Network(ctx, c["net"])
+    st = torch.tensor(c["state"], device="cuda:0")
+    before = st.clone()
+    for prec in ("fp64", "mixed"):
+        best, times = zb.autotune(ctx, net, st, 1.0, 1e-8, 1e-12, precision=prec)
+        print(f"autotune {prec}: best lanes {best}, ms per lane count 1..64: "
+              f"{[round(t, 2) for t in times]}", flush=True)
+        assert torch.equal(st, before)
+        lanes = [1 << i for i in range(7)]
+        timed = {l: t for l, t in zip(lanes, times) if t > 0}
+        assert best in timed
+        # every mapping of this network agrees on statuses and on >= 99% of the zones, so the
+        # fastest one is chosen
+        assert timed[best] == min(timed.values())
+        assert zb.get_mapping(ctx, net, prec) == best
+        out = run_gpu(zb, ctx, c["net"], c["state"][:512], 1.0, 1e-8, 1e-12, precision=prec,
+                      net=net)
+        ref = run_gpu(zb, ctx, c["net"], c["state"][:512], 1.0, 1e-8, 1e-12, precision=prec,
+                      lanes=best, net=net)
+        assert np.array_equal(out[0], ref[0])
+    net.close()
