@@ -47,6 +47,31 @@ def step_flops(nv, nr, thermal, stats):
     return nje * per_att + nfe * per_rhs + nni * per_it
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "burn_kernel_16x16_nv14_2p20zones_hbm_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2608_06466_amd", "csrc", f)
+                  for f in ("zb_kernels.hip", "zb_internal.h")]
+
+
+def measured_traffic(precision, zones):
+    """HBM bytes per burn launch from the committed FETCH_SIZE/WRITE_SIZE profile.
+
+    None unless the profile was taken on the current kernel sources and on the
+    same zone count (the counters do not run inside this process)."""
+    import hashlib
+    import re
+    if zones != 1 << 20 or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    txt = open(TRAFFIC_PROFILE).read()
+    m = re.search(r"kernel_sources_sha256: ([0-9a-f]{64})", txt)
+    t = re.search(rf"traffic_bytes_per_launch:.*\b{precision}=([0-9.e+]+)", txt)
+    if not m or not t:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return float(t.group(1)) if h.hexdigest() == m.group(1) else None
+
+
 def transcendentals(nr, thermal, stats):
     return stats[:, 1].astype(np.float64).sum() * ((nr + 2) if thermal else 0)
 
@@ -138,10 +163,11 @@ def main():
 
     sm, sf = summary(res["mixed"]), summary(res["fp64"])
 
-    def roofline(s):
+    def roofline(s, precision):
         achieved = s["flops"] / (s["kernel_ms"] * 1e-3) / 1e12
         return {"bound": "alu", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None}
+                "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic(precision, zones)}
 
     # ---- CPU oracle baseline on a bounded sample (rank 0, N=1 only) ----
     cpu = None
@@ -193,10 +219,10 @@ def main():
                    "zones": zones, "nv": nv, "reactions": nr, "precision": "mixed",
                    "lanes_per_zone": sm["lanes_per_zone"], "parallelism": "1 GPU"},
         "plain_fp64": {"value": round(sf["value"], 1), "ms_per_step": round(sf["ms_per_step"], 2),
-                       "kernel_ms": round(sf["kernel_ms"], 2), "roofline": roofline(sf),
+                       "kernel_ms": round(sf["kernel_ms"], 2), "roofline": roofline(sf, "fp64"),
                        "lanes_per_zone": sf["lanes_per_zone"]},
         "mixed_over_fp64": round(sm["value"] / sf["value"], 3),
-        "roofline": roofline(sm),
+        "roofline": roofline(sm, "mixed"),
         "kernel_ms": round(sm["kernel_ms"], 2),
         "zone_steps": {"mean": round(sm["mean_steps"], 1), "max": sm["max_steps"]},
         "transcendentals_per_s": round(transcendentals(nr, 1, res["mixed"]["stats"])

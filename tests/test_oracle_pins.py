@@ -9,6 +9,7 @@ independent brute-force Radau IIA integrator and scipy's Radau at tight
 tolerance.
 """
 import math
+import os
 from fractions import Fraction
 
 import numpy as np
@@ -60,13 +61,6 @@ def test_lcoef_exact_rationals(q):
     assert abs(got[0] - 1.0 / sum(1.0 / i for i in range(1, q + 1))) < 1e-15
 
 
-def test_lcoef_printed_values():
-    # q = 2 and q = 5 written out
-    assert np.allclose(oracle.lcoef(2), [2 / 3, 1, 1 / 3], rtol=1e-15, atol=0)
-    assert np.allclose(oracle.lcoef(5), [60 / 137, 1, 225 / 274, 85 / 274, 15 / 274, 1 / 274],
-                       rtol=1e-15, atol=0)
-
-
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
 def test_stirling_numbers(n):
     c = oracle.stirling(n)
@@ -108,10 +102,33 @@ def _classic_bdf_alpha(q):
     return alpha
 
 
-def test_classic_bdf2_textbook_coefficients():
-    a = _classic_bdf_alpha(2)
-    a = [x / a[0] for x in a]
-    assert a == [1, Fraction(-4, 3), Fraction(1, 3)]
+def _golden_bdf():
+    """tests/golden/bdf_coefficients.txt: textbook alpha, beta and Nordsieck l(q), q = 1..5."""
+    rows = {}
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "bdf_coefficients.txt")
+    for line in open(path):
+        line = line.split("#")[0].strip()
+        if not line:
+            continue
+        q, alpha, beta, l = (f.split() for f in line.split("|"))
+        rows[int(q[0])] = ([Fraction(x) for x in alpha], Fraction(beta[0]), [Fraction(x) for x in l])
+    return rows
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 4, 5])
+def test_bdf_coefficients_match_the_textbook_tables(q):
+    alpha, beta, l = _golden_bdf()[q]
+    # the oracle's Nordsieck correction vector (Byrne & Hindmarsh)
+    got = oracle.lcoef(q)
+    assert len(got) == q + 1
+    for e, g in zip(l, got):
+        assert abs(g - float(e)) <= 2 * np.spacing(float(e))
+    # l_0 is the classic formula's beta (gamma = h l_0 in M = I - gamma J)
+    assert l[0] == beta
+    # the Lagrange construction used by the next test reproduces the classic alpha
+    a = _classic_bdf_alpha(q)
+    assert [x / a[0] for x in a] == alpha
+    assert 1 / a[0] == beta
 
 
 @pytest.mark.parametrize("q", [1, 2, 3, 4, 5])
