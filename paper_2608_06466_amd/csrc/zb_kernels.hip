@@ -75,11 +75,17 @@ __device__ __forceinline__ int dpp(int v)
 __device__ __forceinline__ double opq(double v) { asm volatile("" : "+v"(v)); return v; }
 __device__ __forceinline__ float opq(float v) { asm volatile("" : "+v"(v)); return v; }
 
-template <class T>
-__device__ __forceinline__ T xor_lane(T v, int m)
-{
-    return __shfl_xor(v, m, 64);
-}
+// v, made to depend on d (no instruction).  Keeps the scheduler from computing
+// the per-step owner masks of a triangular solve ahead of the dependent chain,
+// which would hold one scalar mask per step live at once.
+template <class D>
+__device__ __forceinline__ int after(int v, D d) { asm volatile("" : "+v"(v) : "v"(d)); return v; }
+
+// A private copy of a wave-uniform integer (no instruction).  Comparisons of
+// the LU and solve loops against the network size are then not shared between
+// those routines, which would keep one scalar mask per column live across a
+// whole step.
+__device__ __forceinline__ int own_copy(int v) { asm volatile("" : "+s"(v)); return v; }
 
 // Compile-time loop: f(std::integral_constant<int, i>) for i = B .. E-1.  Indices of
 // register arrays stay constant expressions even where a loop bound depends on an
@@ -100,7 +106,55 @@ struct OpAdd { template <class T> __device__ T operator()(T a, T b) const { retu
 struct OpMax { template <class T> __device__ T operator()(T a, T b) const { return a > b ? a : b; } };
 struct OpMin { template <class T> __device__ T operator()(T a, T b) const { return a < b ? a : b; } };
 
-// All-reduce over the L lanes of a group; every lane receives the same bits.
+// Exchange across 16-lane rows without LDS (gfx950 v_permlane16_swap /
+// v_permlane32_swap).  Swapping a register with itself leaves, in the pair
+// (r0, r1), this lane's value and that of the lane 16 (32) positions away, in an
+// order that depends on the row; a commutative op of the two is the same in both
+// partner lanes.
+template <int D>
+__device__ __forceinline__ void xswap(unsigned v, unsigned &a, unsigned &b)
+{
+    if constexpr (D == 16) {
+        auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        a = r[0];
+        b = r[1];
+    } else {
+        auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        a = r[0];
+        b = r[1];
+    }
+}
+
+template <int D, class Op>
+__device__ __forceinline__ double xrow(double v, Op op)
+{
+    unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    unsigned a0, b0, a1, b1;
+    xswap<D>((unsigned)(u & 0xffffffffu), a0, b0);
+    xswap<D>((unsigned)(u >> 32), a1, b1);
+    double x = __longlong_as_double((long long)(((unsigned long long)a1 << 32) | a0));
+    double y = __longlong_as_double((long long)(((unsigned long long)b1 << 32) | b0));
+    return op(x, y);
+}
+
+template <int D, class Op>
+__device__ __forceinline__ float xrow(float v, Op op)
+{
+    unsigned a, b;
+    xswap<D>(__float_as_uint(v), a, b);
+    return op(__uint_as_float(a), __uint_as_float(b));
+}
+
+template <int D, class Op>
+__device__ __forceinline__ int xrow(int v, Op op)
+{
+    unsigned a, b;
+    xswap<D>((unsigned)v, a, b);
+    return op((int)a, (int)b);
+}
+
+// All-reduce over the L lanes of a group; every lane receives the same bits
+// (the ops are commutative, and every stage combines the same pair in both lanes).
 template <int L, class T, class Op>
 __device__ __forceinline__ T greduce(T v, Op op)
 {
@@ -108,16 +162,35 @@ __device__ __forceinline__ T greduce(T v, Op op)
     if constexpr (L >= 4) v = op(v, dpp<0x4E>(v));     // quad_perm [2,3,0,1]
     if constexpr (L >= 8) v = op(v, dpp<0x141>(v));    // row_half_mirror
     if constexpr (L >= 16) v = op(v, dpp<0x140>(v));   // row_mirror
-    if constexpr (L >= 32) v = op(v, xor_lane(v, 16));
-    if constexpr (L >= 64) v = op(v, xor_lane(v, 32));
+    if constexpr (L >= 32) v = xrow<16>(v, op);
+    if constexpr (L >= 64) v = xrow<32>(v, op);
     return v;
+}
+
+// Whole-wave groups: the value of the lowest lane whose flag is set, in every
+// lane (zero when no lane is flagged), read with v_readlane.
+template <class T>
+__device__ __forceinline__ T wave_pick(T v, bool flag)
+{
+    unsigned long long m = __ballot(flag);
+    if (m == 0ull) return T(0);
+    const int src = __builtin_ctzll(m);
+    if constexpr (sizeof(T) == 8) {
+        unsigned long long u = (unsigned long long)__double_as_longlong(v);
+        unsigned lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffu), src);
+        unsigned hi = __builtin_amdgcn_readlane((int)(u >> 32), src);
+        return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    } else {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+    }
 }
 
 // Value held by the single owner lane of the group, delivered to every lane.
 template <int L, class T>
 __device__ __forceinline__ T gbcast(T v, bool owner)
 {
-    return greduce<L>(owner ? v : T(0), OpAdd());
+    if constexpr (L == 64) return wave_pick(v, owner);
+    else return greduce<L>(owner ? v : T(0), OpAdd());
 }
 
 // Same, through a group LDS slot: one store by the owner, one load by everyone.
@@ -279,7 +352,7 @@ __device__ __forceinline__ double wrms(const Ctx &c, const Zone<NVP, L, LT> &z,
 // f(y) for the group's zone; with WANTJ also assembles M = I - gamma J (and
 // its FP32 scaling) in registers.  y and f are by local row.
 template <bool WANTJ, int NVP, int L, class LT>
-__device__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const double (&yv)[Zone<NVP, L, LT>::RPL],
+__device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const double (&yv)[Zone<NVP, L, LT>::RPL],
                      double (&fo)[Zone<NVP, L, LT>::RPL], double gamma)
 {
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
@@ -423,11 +496,11 @@ __device__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const double (&yv)[Zone<
 // --------------------------------------------------------------- LU / solve
 
 template <int NVP, int L, class LT>
-__device__ void lu_factor(const Ctx &c, Zone<NVP, L, LT> &z)
+__device__ __forceinline__ void lu_factor(const Ctx &c, Zone<NVP, L, LT> &z)
 {
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
     LT *prow = (LT *)(c.S + c.lay.prow);
-    const int nv = c.net.nv;
+    const int nv = own_copy(c.net.nv);
     sfor<0, RPL>([&](auto S) { z.pstep[S] = 127; });
     sfor<0, NVP>([&](auto K) {
         constexpr int k = K;
@@ -443,17 +516,28 @@ __device__ void lu_factor(const Ctx &c, Zone<NVP, L, LT> &z)
             }
         });
         double gm = greduce<L>(bv, OpMax());
-        int p = greduce<L>(bv == gm ? bi : (1 << 20), OpMin());
+        int p;
+        if constexpr (L == 64 && RPL == 1) {
+            // one row per lane: the lowest flagged lane is the lowest row
+            unsigned long long m = __ballot(bv == gm && bi < (1 << 20));
+            p = m ? (int)__builtin_ctzll(m) : (1 << 20);
+        } else {
+            p = greduce<L>(bv == gm ? bi : (1 << 20), OpMin());
+        }
         int pl = p & (L - 1);
         int ps = p / L;
         if (c.gl == pl) {
             sfor<k, NVP>([&](auto J) {
-                LT v = opq(z.M[0][J]);
-                sfor<1, RPL>([&](auto S) {
-                    LT cand = opq(z.M[S][J]);
-                    v = (ps == S) ? cand : v;
-                });
-                prow[J] = v;
+                if constexpr (RPL == 1) {
+                    prow[J] = z.M[0][J];
+                } else {
+                    LT v = opq(z.M[0][J]);
+                    sfor<1, RPL>([&](auto S) {
+                        LT cand = opq(z.M[S][J]);
+                        v = (ps == S) ? cand : v;
+                    });
+                    prow[J] = v;
+                }
             });
         }
         lds_fence();
@@ -467,7 +551,11 @@ __device__ void lu_factor(const Ctx &c, Zone<NVP, L, LT> &z)
             bool act = z.pstep[S] > k;
             LT l = act ? z.M[S][k] * rinv : LT(0);
             if (act) z.M[S][k] = l;
-            sfor<k + 1, NVP>([&](auto J) { z.M[S][J] = fma(-l, prow[J], z.M[S][J]); });
+            sfor<k + 1, NVP>([&](auto J) {
+                z.M[S][J] = fma(-l, prow[J], z.M[S][J]);
+                // bound how many pivot-row loads are in flight (register pressure)
+                if constexpr (NVP > 24 && J % 8 == 7) asm volatile("" ::: "memory");
+            });
         });
         lds_fence();
     });
@@ -475,11 +563,11 @@ __device__ void lu_factor(const Ctx &c, Zone<NVP, L, LT> &z)
 
 // Solve M x = b: b by local row in, x by local component out (same slots).
 template <int NVP, int L, class LT>
-__device__ void lu_solve(const Ctx &c, const Zone<NVP, L, LT> &z, double (&b)[Zone<NVP, L, LT>::RPL])
+__device__ __forceinline__ void lu_solve(const Ctx &c, const Zone<NVP, L, LT> &z, double (&b)[Zone<NVP, L, LT>::RPL])
 {
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
     constexpr bool MIXED = sizeof(LT) == 4;
-    const int nv = c.net.nv;
+    const int nv = own_copy(c.net.nv);
     LT bb[RPL], x[RPL];
     sfor<0, RPL>([&](auto S) {
         bb[S] = MIXED ? (LT)(b[S] * (double)z.rs[S]) : (LT)b[S];
@@ -490,13 +578,15 @@ __device__ void lu_solve(const Ctx &c, const Zone<NVP, L, LT> &z, double (&b)[Zo
         if (k >= nv) return;
         LT v = LT(0);
         bool own = false;
+        int ps[RPL];
         sfor<0, RPL>([&](auto S) {
+            ps[S] = after(z.pstep[S], bb[S]);
             LT cand = opq(bb[S]);
-            if (z.pstep[S] == k) { v = cand; own = true; }
+            if (ps[S] == k) { v = cand; own = true; }
         });
         LT zk = gbcast_solve<L>(v, own, c.S + c.lay.xch);
         sfor<0, RPL>([&](auto S) {
-            if (z.pstep[S] > k) bb[S] = fma(-z.M[S][k], zk, bb[S]);
+            if (ps[S] > k) bb[S] = fma(-z.M[S][k], zk, bb[S]);
         });
     });
     sfor<0, NVP>([&](auto KK) {
@@ -504,13 +594,15 @@ __device__ void lu_solve(const Ctx &c, const Zone<NVP, L, LT> &z, double (&b)[Zo
         if (k >= nv) return;
         LT v = LT(0);
         bool own = false;
+        int ps[RPL];
         sfor<0, RPL>([&](auto S) {
+            ps[S] = after(z.pstep[S], bb[S]);
             LT cand = opq(bb[S]) * opq(z.dinv[S]);
-            if (z.pstep[S] == k) { v = cand; own = true; }
+            if (ps[S] == k) { v = cand; own = true; }
         });
         LT xk = gbcast_solve<L>(v, own, c.S + c.lay.xch);
         sfor<0, RPL>([&](auto S) {
-            if (z.pstep[S] < k) bb[S] = fma(-z.M[S][k], xk, bb[S]);
+            if (ps[S] < k) bb[S] = fma(-z.M[S][k], xk, bb[S]);
         });
         if (c.gl == (k % L)) x[k / L] = xk;
     });
@@ -587,7 +679,7 @@ enum { RUNNING = -1 };
 
 // Start of a zone: load, Hairer-Norsett-Wanner initial step.  Returns RUNNING or a status.
 template <int NVP, int L, class LT>
-__device__ int zone_start(const Ctx &c, Zone<NVP, L, LT> &z)
+__device__ __forceinline__ int zone_start(const Ctx &c, Zone<NVP, L, LT> &z)
 {
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
     const DevNet &N = c.net;
@@ -646,7 +738,7 @@ __device__ int zone_start(const Ctx &c, Zone<NVP, L, LT> &z)
 
 // One step attempt.  Returns RUNNING, or the zone's final status.
 template <int NVP, int L, class LT>
-__device__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z, int max_steps)
+__device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z, int max_steps)
 {
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
     const double tau = 0.03;
@@ -850,7 +942,7 @@ __device__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z, int max_steps)
 }
 
 template <int NVP, int L, class LT>
-__device__ void zone_finish(const Ctx &c, Zone<NVP, L, LT> &z, int status, const BurnArgs &A)
+__device__ __forceinline__ void zone_finish(const Ctx &c, Zone<NVP, L, LT> &z, int status, const BurnArgs &A)
 {
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
     const int ns = c.net.ns;
@@ -922,14 +1014,17 @@ __device__ __forceinline__ void load_segment(Ctx &c, const BurnArgs &A, int seg,
 // Persistent kernel.  Each wave works through the segments in order; within a
 // segment every group of L lanes pulls zones from the segment's queue until it
 // is empty, and the wave moves on once all its groups have found it empty.
-#ifndef ZB_WAVES_PER_EU
-#define ZB_WAVES_PER_EU 0
-#endif
+//
+// Occupancy.  The 48-row kernels would take ~320 VGPRs and run one wave per
+// SIMD; bounding them to two waves costs a few spilled registers and is ~20 %
+// faster (the LU and solve chains are latency-bound).  The smaller kernels are
+// left to the compiler (a bound there only adds spills).
+template <int NVP, int L>
+constexpr int min_waves_per_eu() { return (NVP >= 48 && L == 64) ? 2 : 1; }
+
 template <int NVP, int L, class LT>
 __global__ __launch_bounds__(64)
-#if ZB_WAVES_PER_EU > 0
-__attribute__((amdgpu_waves_per_eu(ZB_WAVES_PER_EU)))
-#endif
+__attribute__((amdgpu_waves_per_eu(min_waves_per_eu<NVP, L>())))
 void burn_kernel(BurnArgs A)
 {
     extern __shared__ double smem[];
