@@ -114,9 +114,14 @@ zb_err zb_burn(zb_context *ctx, const zb_network *net, double *state, int64_t zo
    this context since the previous zb_sync ended with a non-OK status (the count is cleared). */
 zb_err zb_sync(zb_context *ctx, void *stream, int64_t *n_failed_zones);
 
-/* Several networks in ONE persistent launch (zones of uneven cost and different sizes share a
-   device work queue).  Each segment is burned exactly as zb_burn would burn it alone with the
-   same opts and lanes per zone. */
+/* Several networks in one call (the paper's loop over zones, with the zones of different
+   networks and tolerances batched).  Segments that use the same kernel (same padded size,
+   lanes per zone and precision; up to 8 per launch) share ONE persistent launch with a device
+   work queue per segment, so zones of uneven cost keep every wave busy.  Different kernel
+   classes run as concurrent persistent launches on side streams forked from `stream` and
+   joined back into it (costliest class first), so one class's tail is filled by the others.
+   Each segment is burned exactly (bitwise) as zb_burn would burn it alone with the same opts
+   and lanes per zone.  Errors as zb_burn; the call may be captured in a HIP graph. */
 typedef struct {
     const zb_network *net;
     double *state;              /* DEVICE [zones][n_species+1] */
@@ -128,6 +133,74 @@ typedef struct {
 } zb_segment;
 zb_err zb_burn_batch(zb_context *ctx, const zb_segment *segs, int32_t n_seg, const zb_opts *opts,
                      void *stream);
+
+/* Fixed-shape repeats as a HIP graph: the burn of these segments (buffers, sizes, tolerances
+   and options fixed at creation) is captured once and replayed by zb_graph_launch, each
+   replay burning whatever the buffers then hold.  The graph owns its work-queue counters
+   (cleared by a kernel inside the graph, no memset node); replays of one graph must not
+   overlap in time (launch them on one stream, or order them).  Failed zones count towards
+   zb_sync of the context.  The buffers must outlive the graph. */
+typedef struct zb_graph zb_graph;
+zb_err zb_graph_create(zb_context *ctx, const zb_segment *segs, int32_t n_seg, const zb_opts *opts,
+                       zb_graph **out);
+zb_err zb_graph_launch(zb_graph *graph, void *stream);
+zb_err zb_graph_destroy(zb_graph *graph);
+
+/* ------------------------------------------------------------------------------------------
+   Serving: continuous batching of burn requests (the paper keeps simulation state resident in
+   GPU memory and burns it there; here many independent requests of different networks, sizes
+   and tolerances share one GPU).
+
+   zb_server_submit copies the request's HOST input and queues it.  Requests are admitted
+   first come, first served as soon as their device state (state, status, counters, scales)
+   fits in the server's HBM budget, which is allocated once at creation (no device allocation
+   per request).  A scheduler thread cuts admitted requests into slices of zones and keeps
+   persistent launches in flight on several streams; a launch holds slices of up to 8
+   requests that use the same kernel class, and a request arriving while others run joins the
+   next launch, its kernels overlapping the launches in flight.  Results stay in device memory
+   until zb_server_fetch copies them out and frees the memory.  Every zone is burned exactly
+   (bitwise) as zb_burn would burn it with opts = zb_server_opts.burn, so a request's result
+   is the same alone and in any mix.  Latencies are measured on the host from submit.
+   ------------------------------------------------------------------------------------------ */
+typedef struct {
+    size_t hbm_budget_bytes;       /* device bytes for resident requests (>= 1 MiB), allocated once */
+    int32_t streams;               /* concurrent launch streams, 0 = 4 (1..8) */
+    int32_t launches_per_stream;   /* launches queued per stream, 0 = 2 (1..4) */
+    int64_t slice_zones;           /* zones per slice, 0 = half of the GPU's resident zones for
+                                      the request's kernel */
+    int32_t max_pending;           /* requests waiting for admission before ZB_EBUSY, 0 = 1024 */
+    int32_t reserved;
+    zb_opts burn;                  /* precision, mapping and max_steps of every request */
+} zb_server_opts;
+
+typedef struct {
+    int64_t zones, zones_ok;
+    double queue_s;          /* submit -> admission (device memory granted) */
+    double first_launch_s;   /* submit -> first slice launched */
+    double latency_s;        /* submit -> last slice finished on the device */
+} zb_request_info;
+
+typedef struct {
+    int64_t requests_done, zones_done, launches, pending, active, bytes_in_use, peak_bytes_in_use;
+} zb_server_totals;
+
+/* ZB_EINVAL on bad options; ZB_ENOMEM if the budget cannot be allocated. */
+zb_err zb_server_create(zb_context *ctx, const zb_server_opts *opts, zb_server **out);
+/* host_state: HOST [zones][n_species+1]; host_rate_scale: HOST [zones][n_reactions] or NULL.
+   Both are copied before the call returns.  ZB_EINVAL for bad arguments or a request larger
+   than the whole budget; ZB_EBUSY when max_pending requests are already waiting. */
+zb_err zb_server_submit(zb_server *srv, const zb_network *net, const double *host_state,
+                        int64_t zones, double dt, double rtol, double atol,
+                        const double *host_rate_scale, uint64_t *ticket);
+/* Wait up to timeout_s seconds (0: just test) for a request; *done = 1 when it has finished. */
+zb_err zb_server_wait(zb_server *srv, uint64_t ticket, double timeout_s, int32_t *done);
+/* Copy a finished request's results to HOST buffers (any may be NULL) and release it.
+   ZB_EBUSY if it has not finished, ZB_ENOTFOUND for an unknown or already fetched ticket. */
+zb_err zb_server_fetch(zb_server *srv, uint64_t ticket, double *host_state_out,
+                       int32_t *zone_status_out, zb_zone_stats *stats_out, zb_request_info *info);
+zb_err zb_server_stats(zb_server *srv, zb_server_totals *out);
+/* Waits for the launches in flight, then frees everything; unfetched requests are dropped. */
+zb_err zb_server_destroy(zb_server *srv);
 
 /* Lanes per zone the library uses for (network, precision) when opts->mapping is AUTO. */
 zb_err zb_get_mapping(zb_context *ctx, const zb_network *net, int32_t precision, int32_t *lanes);

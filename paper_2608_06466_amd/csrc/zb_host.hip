@@ -11,14 +11,14 @@
 #include <string>
 #include <vector>
 
-#include "zb_internal.h"
-#include "zoneburn.h"
+#include "zb_host_internal.h"
 
 using namespace zb;
+using namespace zbh;
 
 static thread_local std::string g_last_error;
 
-static zb_err fail(zb_err e, const char *fmt, ...)
+zb_err zbh::fail(zb_err e, const char *fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -28,48 +28,6 @@ static zb_err fail(zb_err e, const char *fmt, ...)
     g_last_error = buf;
     return e;
 }
-
-#define HIP_TRY(call)                                                                      \
-    do {                                                                                   \
-        hipError_t e_ = (call);                                                            \
-        if (e_ != hipSuccess)                                                              \
-            return fail(ZB_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));        \
-    } while (0)
-
-namespace {
-constexpr int QUEUE_SLOTS = 1024;
-
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard()
-    {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-}  // namespace
-
-struct zb_context {
-    int device = 0;
-    int cus = 0;
-    unsigned long long *ws = nullptr;   // [0] failed zones, then QUEUE_SLOTS x MAXSEG queue counters
-    int next_slot = 0;
-    std::mutex mu;
-    // autotuned lanes per zone, keyed by (nv, nr, precision)
-    struct Tuned { int nv, nr, prec, lanes; };
-    std::vector<Tuned> tuned;
-};
-
-struct zb_network {
-    zb_context *ctx = nullptr;
-    DevNet dn{};
-    void *dmem = nullptr;
-};
 
 // ------------------------------------------------------------------ context
 
@@ -111,6 +69,9 @@ extern "C" zb_err zb_context_destroy(zb_context *ctx)
         DeviceGuard g(ctx->device);
         (void)hipDeviceSynchronize();
         (void)hipFree(ctx->ws);
+        for (auto s : ctx->side) (void)hipStreamDestroy(s);
+        for (auto e : ctx->join) (void)hipEventDestroy(e);
+        if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     }
     delete ctx;
     return ZB_OK;
@@ -232,7 +193,7 @@ static int default_lanes(int nv)
 }
 
 // Smallest kernel with nvp >= nv for the given lanes and precision.
-static const KernelInfo *find_kernel(int nv, int lanes, int mixed)
+const KernelInfo *zbh::find_kernel(int nv, int lanes, int mixed)
 {
     const KernelInfo *tab;
     int n = kernel_table(&tab);
@@ -244,7 +205,7 @@ static const KernelInfo *find_kernel(int nv, int lanes, int mixed)
     return best;
 }
 
-static int lanes_for(zb_context *ctx, const zb_network *net, int prec, const zb_opts *o)
+int zbh::lanes_for(zb_context *ctx, const zb_network *net, int prec, const zb_opts *o)
 {
     if (o && o->mapping != ZB_MAP_AUTO) return o->mapping;
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -274,7 +235,7 @@ static bool valid_ptr(const void *p, int device)
     return false;
 }
 
-static zb_err check_segment(zb_context *ctx, const zb_segment &s)
+zb_err zbh::check_segment(zb_context *ctx, const zb_segment &s)
 {
     if (!s.net) return fail(ZB_EINVAL, "NULL network");
     if (s.net->ctx != ctx) return fail(ZB_EINVAL, "network belongs to another context");
@@ -292,9 +253,28 @@ static zb_err check_segment(zb_context *ctx, const zb_segment &s)
     return ZB_OK;
 }
 
-// One persistent launch over segments that all use the same kernel.
+static size_t launch_lds(const KernelInfo *k, int max_nr)
+{
+    const int G = 64 / k->lanes;
+    const int rpl = (k->nvp + k->lanes - 1) / k->lanes;
+    const LdsLayout lay = lds_layout(k->nvp, k->lanes * rpl, max_nr);
+    return (size_t)G * lay.total * sizeof(double);
+}
+
+int zbh::blocks_per_cu(const KernelInfo *k, int max_nr)
+{
+    const size_t lds = launch_lds(k, max_nr);
+    if (lds > 160 * 1024) return 0;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k->fn, 64, lds) != hipSuccess) return 0;
+    return per_cu;
+}
+
+// One persistent launch over segments that all use the same kernel.  queue:
+// MAXSEG device counters the launch clears first; nfail: failed-zone counter.
 static zb_err launch_segments(zb_context *ctx, const KernelInfo *k, const zb_segment *segs, int n,
-                              int max_steps, hipStream_t stream, float *ms_out = nullptr)
+                              int max_steps, hipStream_t stream, unsigned long long *queue,
+                              unsigned long long *nfail, float *ms_out)
 {
     BurnArgs A;
     memset(&A, 0, sizeof A);
@@ -318,19 +298,11 @@ static zb_err launch_segments(zb_context *ctx, const KernelInfo *k, const zb_seg
     A.nseg = n;
     A.max_nr = max_nr;
     A.max_steps = max_steps;
-    int slot;
-    {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        slot = ctx->next_slot;
-        ctx->next_slot = (ctx->next_slot + 1) % QUEUE_SLOTS;
-    }
-    A.queue = ctx->ws + 1 + (size_t)slot * MAXSEG;
-    A.nfail = ctx->ws;
+    A.queue = queue;
+    A.nfail = nfail;
 
     const int G = 64 / k->lanes;
-    const int rpl = (k->nvp + k->lanes - 1) / k->lanes;
-    const LdsLayout lay = lds_layout(k->nvp, k->lanes * rpl, max_nr);
-    const size_t lds = (size_t)G * lay.total * sizeof(double);
+    const size_t lds = launch_lds(k, max_nr);
     if (lds > 160 * 1024) return fail(ZB_EUNSUPPORTED, "LDS need %zu bytes exceeds 160 KiB", lds);
     int per_cu = 0;
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k->fn, 64, lds));
@@ -356,14 +328,21 @@ static zb_err launch_segments(zb_context *ctx, const KernelInfo *k, const zb_seg
     return ZB_OK;
 }
 
-static zb_err burn_impl(zb_context *ctx, const zb_segment *segs, int n, const zb_opts *opts,
-                        void *stream, int force_lanes = 0, float *ms_out = nullptr)
+namespace {
+// Segments that share a kernel: one persistent launch.
+struct Group {
+    const KernelInfo *k;
+    std::vector<zb_segment> segs;
+    double cost;   // relative device time, for ordering
+};
+}  // namespace
+
+static zb_err plan_groups(zb_context *ctx, const zb_segment *segs, int n, const zb_opts *opts,
+                          int force_lanes, std::vector<Group> &out)
 {
-    if (!ctx) return fail(ZB_EINVAL, "NULL context");
     if (n < 0 || (n > 0 && !segs)) return fail(ZB_EINVAL, "bad segment list");
     const int prec = opts ? opts->precision : ZB_FP64;
     if (prec != ZB_FP64 && prec != ZB_MIXED) return fail(ZB_EINVAL, "precision %d", prec);
-    int max_steps = (opts && opts->max_steps > 0) ? opts->max_steps : 100000;
     if (opts && opts->mapping != ZB_MAP_AUTO &&
         (opts->mapping < 1 || opts->mapping > 64 || (opts->mapping & (opts->mapping - 1))))
         return fail(ZB_EINVAL, "mapping must be 0 or a power of two 1..64");
@@ -371,29 +350,98 @@ static zb_err burn_impl(zb_context *ctx, const zb_segment *segs, int n, const zb
         zb_err e = check_segment(ctx, segs[i]);
         if (e != ZB_OK) return e;
     }
-    DeviceGuard g(ctx->device);
-    // group segments by kernel; each group is one persistent launch
-    std::vector<const KernelInfo *> ker(n);
+    out.clear();
     for (int i = 0; i < n; ++i) {
+        if (segs[i].zones == 0) continue;
         int lanes = force_lanes ? force_lanes : lanes_for(ctx, segs[i].net, prec, opts);
-        ker[i] = find_kernel(segs[i].net->dn.nv, lanes, prec == ZB_MIXED);
-        if (!ker[i])
+        const KernelInfo *k = find_kernel(segs[i].net->dn.nv, lanes, prec == ZB_MIXED);
+        if (!k)
             return fail(ZB_EUNSUPPORTED, "no kernel for nv=%d with %d lanes per zone (%s)",
                         segs[i].net->dn.nv, lanes, prec == ZB_MIXED ? "mixed" : "fp64");
-    }
-    std::vector<bool> done(n, false);
-    for (int i = 0; i < n; ++i) {
-        if (done[i]) continue;
-        std::vector<zb_segment> grp;
-        for (int j = i; j < n; ++j) {
-            if (!done[j] && ker[j] == ker[i] && (int)grp.size() < MAXSEG) {
-                grp.push_back(segs[j]);
-                done[j] = true;
-            }
+        Group *g = nullptr;
+        for (auto &x : out)
+            if (x.k == k && x.segs.size() < (size_t)MAXSEG) g = &x;
+        if (!g) {
+            out.push_back(Group{k, {}, 0.0});
+            g = &out.back();
         }
-        zb_err e = launch_segments(ctx, ker[i], grp.data(), (int)grp.size(), max_steps,
-                                   (hipStream_t)stream, ms_out);
+        g->segs.push_back(segs[i]);
+        // per-step work grows roughly with the square of the padded size
+        g->cost += (double)segs[i].zones * (double)k->nvp * (double)k->nvp;
+    }
+    std::stable_sort(out.begin(), out.end(), [](const Group &a, const Group &b) { return a.cost > b.cost; });
+    return ZB_OK;
+}
+
+int zbh::count_launches(zb_context *ctx, const zb_segment *segs, int n, const zb_opts *opts, int *launches)
+{
+    std::vector<Group> groups;
+    zb_err e = plan_groups(ctx, segs, n, opts, 0, groups);
+    if (e != ZB_OK) return e;
+    *launches = (int)groups.size();
+    return ZB_OK;
+}
+
+static zb_err side_streams(zb_context *ctx, int need)
+{
+    while ((int)ctx->side.size() < need) {
+        hipStream_t s = nullptr;
+        hipEvent_t ev = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        ctx->side.push_back(s);
+        ctx->join.push_back(ev);
+    }
+    if (!ctx->fork) HIP_TRY(hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming));
+    return ZB_OK;
+}
+
+zb_err zbh::burn_impl(zb_context *ctx, const zb_segment *segs, int n, const zb_opts *opts,
+                      void *stream, int force_lanes, float *ms_out, const Workspace *ws)
+{
+    if (!ctx) return fail(ZB_EINVAL, "NULL context");
+    std::vector<Group> groups;
+    zb_err e = plan_groups(ctx, segs, n, opts, force_lanes, groups);
+    if (e != ZB_OK) return e;
+    if (groups.empty()) return ZB_OK;
+    const int max_steps = (opts && opts->max_steps > 0) ? opts->max_steps : 100000;
+    const int ng = (int)groups.size();
+    if (ws && ng > ws->launches)
+        return fail(ZB_EINVAL, "workspace holds queues for %d launches, %d needed", ws->launches, ng);
+    DeviceGuard g(ctx->device);
+    std::vector<unsigned long long *> queue(ng);
+    unsigned long long *nfail = ws ? ws->nfail : ctx->ws;
+    if (ws) {
+        for (int i = 0; i < ng; ++i) queue[i] = ws->queue + (size_t)i * MAXSEG;
+    } else {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        for (int i = 0; i < ng; ++i) {
+            queue[i] = ctx->ws + 1 + (size_t)ctx->next_slot * MAXSEG;
+            ctx->next_slot = (ctx->next_slot + 1) % QUEUE_SLOTS;
+        }
+    }
+    hipStream_t s0 = (hipStream_t)stream;
+    if (ng == 1)
+        return launch_segments(ctx, groups[0].k, groups[0].segs.data(), (int)groups[0].segs.size(),
+                               max_steps, s0, queue[0], nfail, ms_out);
+    // Several kernel classes: the costliest runs on the caller's stream and the
+    // others on side streams forked from it and joined back, so the classes share
+    // the GPU (a class's tail is filled by the others) instead of running in turn.
+    std::lock_guard<std::mutex> lk(ctx->fork_mu);
+    const int nside = std::min(ng - 1, MAX_SIDE_STREAMS);
+    e = side_streams(ctx, nside);
+    if (e != ZB_OK) return e;
+    HIP_TRY(hipEventRecord(ctx->fork, s0));
+    for (int j = 0; j < nside; ++j) HIP_TRY(hipStreamWaitEvent(ctx->side[j], ctx->fork, 0));
+    for (int i = 0; i < ng; ++i) {
+        hipStream_t s = i == 0 ? s0 : ctx->side[(i - 1) % nside];
+        e = launch_segments(ctx, groups[i].k, groups[i].segs.data(), (int)groups[i].segs.size(),
+                            max_steps, s, queue[i], nfail, nullptr);
         if (e != ZB_OK) return e;
+    }
+    for (int j = 0; j < nside; ++j) {
+        HIP_TRY(hipEventRecord(ctx->join[j], ctx->side[j]));
+        HIP_TRY(hipStreamWaitEvent(s0, ctx->join[j], 0));
     }
     return ZB_OK;
 }
@@ -434,6 +482,84 @@ extern "C" zb_err zb_sync(zb_context *ctx, void *stream, int64_t *n_failed)
     }
     if (n_failed) *n_failed = (int64_t)nf;
     return nf ? ZB_EZONES : ZB_OK;
+}
+
+// -------------------------------------------------------------------- graphs
+
+struct zb_graph {
+    zb_context *ctx = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    unsigned long long *queues = nullptr;   // launches x MAXSEG, private to this graph
+};
+
+extern "C" zb_err zb_graph_create(zb_context *ctx, const zb_segment *segs, int32_t n_seg,
+                                  const zb_opts *opts, zb_graph **out)
+{
+    if (!ctx || !out) return fail(ZB_EINVAL, "NULL argument");
+    *out = nullptr;
+    int launches = 0;
+    zb_err e = (zb_err)count_launches(ctx, segs, n_seg, opts, &launches);   // validates everything
+    if (e != ZB_OK) return e;
+    DeviceGuard g(ctx->device);
+    zb_graph *G = new (std::nothrow) zb_graph();
+    if (!G) return fail(ZB_ENOMEM, "host allocation failed");
+    G->ctx = ctx;
+    const size_t qbytes = sizeof(unsigned long long) * MAXSEG * (size_t)std::max(launches, 1);
+    if (hipMalloc((void **)&G->queues, qbytes) != hipSuccess) {
+        delete G;
+        return fail(ZB_ENOMEM, "graph queue allocation failed");
+    }
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipFree(G->queues);
+        delete G;
+        return fail(ZB_EDEVICE, "stream creation failed");
+    }
+    Workspace ws{G->queues, std::max(launches, 1), ctx->ws};
+    e = ZB_OK;
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        e = fail(ZB_EDEVICE, "hipStreamBeginCapture failed");
+    } else {
+        zb_err eb = burn_impl(ctx, segs, n_seg, opts, s, 0, nullptr, &ws);
+        hipError_t ec = hipStreamEndCapture(s, &G->graph);
+        if (eb != ZB_OK) e = eb;
+        else if (ec != hipSuccess) e = fail(ZB_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(ec));
+        else if (hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0) != hipSuccess)
+            e = fail(ZB_EDEVICE, "hipGraphInstantiate failed");
+    }
+    (void)hipStreamDestroy(s);
+    if (e != ZB_OK) {
+        if (G->exec) (void)hipGraphExecDestroy(G->exec);
+        if (G->graph) (void)hipGraphDestroy(G->graph);
+        (void)hipFree(G->queues);
+        delete G;
+        return e;
+    }
+    *out = G;
+    return ZB_OK;
+}
+
+extern "C" zb_err zb_graph_launch(zb_graph *G, void *stream)
+{
+    if (!G) return fail(ZB_EINVAL, "NULL graph");
+    DeviceGuard g(G->ctx->device);
+    HIP_TRY(hipGraphLaunch(G->exec, (hipStream_t)stream));
+    return ZB_OK;
+}
+
+extern "C" zb_err zb_graph_destroy(zb_graph *G)
+{
+    if (!G) return ZB_OK;
+    {
+        DeviceGuard g(G->ctx->device);
+        (void)hipDeviceSynchronize();
+        if (G->exec) (void)hipGraphExecDestroy(G->exec);
+        if (G->graph) (void)hipGraphDestroy(G->graph);
+        (void)hipFree(G->queues);
+    }
+    delete G;
+    return ZB_OK;
 }
 
 // ----------------------------------------------------------------- autotune

@@ -1,0 +1,86 @@
+// Host-side internals shared by the runtime files of libzoneburn (not part of the ABI).
+#pragma once
+
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "zb_internal.h"
+#include "zoneburn.h"
+
+namespace zbh {
+
+zb_err fail(zb_err e, const char *fmt, ...);
+
+#define HIP_TRY(call)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return ::zbh::fail(ZB_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int QUEUE_SLOTS = 1024;
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+constexpr int MAX_SIDE_STREAMS = 3;
+
+// Device counters a call works with: per launch, MAXSEG zone-queue counters
+// (cleared by the launch itself), and one failed-zone counter.
+struct Workspace {
+    unsigned long long *queue;   // launches x MAXSEG
+    int launches;
+    unsigned long long *nfail;
+};
+
+const zb::KernelInfo *find_kernel(int nv, int lanes, int mixed);
+int lanes_for(zb_context *ctx, const zb_network *net, int prec, const zb_opts *o);
+zb_err check_segment(zb_context *ctx, const zb_segment &s);
+// Validates the segments and launches them (one persistent launch per kernel
+// class) on `stream`.  ws = nullptr takes a rotating slot of the context.
+zb_err burn_impl(zb_context *ctx, const zb_segment *segs, int n, const zb_opts *opts, void *stream,
+                 int force_lanes = 0, float *ms_out = nullptr, const Workspace *ws = nullptr);
+// Number of persistent launches (kernel classes) a call with these segments makes.
+int count_launches(zb_context *ctx, const zb_segment *segs, int n, const zb_opts *opts, int *launches);
+// Resident workgroups of kernel k per CU with the LDS a launch over networks of
+// up to max_nr reactions needs (0 if it does not fit).
+int blocks_per_cu(const zb::KernelInfo *k, int max_nr);
+
+}  // namespace zbh
+
+struct zb_context {
+    int device = 0;
+    int cus = 0;
+    unsigned long long *ws = nullptr;   // [0] failed zones, then QUEUE_SLOTS x MAXSEG queue counters
+    int next_slot = 0;
+    std::mutex mu;
+    // autotuned lanes per zone, keyed by (nv, nr, precision)
+    struct Tuned { int nv, nr, prec, lanes; };
+    std::vector<Tuned> tuned;
+    // side streams for calls that launch several kernel classes (default priority)
+    std::mutex fork_mu;
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> join;
+    hipEvent_t fork = nullptr;
+};
+
+struct zb_network {
+    zb_context *ctx = nullptr;
+    zb::DevNet dn{};
+    void *dmem = nullptr;
+};

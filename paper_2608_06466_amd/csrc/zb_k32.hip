@@ -1,0 +1,16 @@
+// Instantiations of the burn kernel: 32, 32, double, 0, 32, 32, float, 1 (padded rows, lanes per zone, LU type).
+#include "zb_burn_kernel.h"
+
+namespace zb {
+
+int kernels_32(const KernelInfo **out)
+{
+    static const KernelInfo t[] = {
+        ZB_K(32, 32, double, 0),
+        ZB_K(32, 32, float, 1),
+    };
+    *out = t;
+    return (int)(sizeof(t) / sizeof(t[0]));
+}
+
+}  // namespace zb

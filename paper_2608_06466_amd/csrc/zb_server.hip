@@ -1,0 +1,571 @@
+// Burn server: continuous batching of burn requests on one GPU.
+//
+// A request (network, zones, dt, tolerances, host input) is copied at submit,
+// queued, and admitted first-come-first-served as soon as its device state fits
+// in the server's HBM budget (one arena, allocated once, so no allocation on
+// the request path).  Admitted requests are cut into slices of zones; a
+// scheduler thread keeps a few persistent launches in flight on several
+// streams, each launch holding up to MAXSEG slices of requests that use the
+// same kernel class (any network or tolerance of that class).  Requests that
+// arrive while others run join the next launch, and their kernels overlap the
+// ones in flight (a launch's tail is filled by the next).  Results stay in
+// device memory until fetched.  A zone's result depends only on its own input
+// and the kernel class, so it is the same whether the request ran alone or in
+// a mix.
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <thread>
+
+#include "zb_host_internal.h"
+
+using namespace zb;
+using namespace zbh;
+
+namespace {
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+constexpr size_t ALIGN = 256;
+
+// First-fit allocator over one device block; offsets only, no device access.
+class Arena {
+public:
+    void init(size_t bytes)
+    {
+        free_.clear();
+        free_[0] = bytes;
+        size_ = bytes;
+        used_ = 0;
+    }
+    bool alloc(size_t bytes, size_t *off)
+    {
+        bytes = (bytes + ALIGN - 1) & ~(ALIGN - 1);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                size_t rest = it->second - bytes, at = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                used_ += bytes;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        bytes = (bytes + ALIGN - 1) & ~(ALIGN - 1);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t used() const { return used_; }
+    size_t size() const { return size_; }
+
+private:
+    std::map<size_t, size_t> free_;
+    size_t size_ = 0, used_ = 0;
+};
+
+enum ReqState { PENDING, ADMITTED, DONE };
+
+struct Request {
+    uint64_t ticket = 0;
+    const zb_network *net = nullptr;
+    const KernelInfo *k = nullptr;
+    int row = 0;
+    int64_t zones = 0;
+    double dt = 0, rtol = 0, atol = 0;
+    std::vector<double> in_state, in_scale;
+    size_t off = 0, bytes = 0;
+    double *state = nullptr, *scale = nullptr;
+    int32_t *status = nullptr;
+    zb_zone_stats *stats = nullptr;
+    hipEvent_t uploaded = nullptr;
+    int64_t next = 0;        // first zone not yet in a launch
+    int64_t finished = 0;    // zones whose launch has completed
+    ReqState st = PENDING;
+    double t_submit = 0, t_admit = 0, t_first = 0, t_done = 0;
+};
+
+struct Launch {
+    hipEvent_t done = nullptr;
+    int stream = 0;
+    int qblock = 0;
+    std::vector<std::pair<Request *, int64_t>> parts;
+};
+
+}  // namespace
+
+struct zb_server {
+    zb_context *ctx = nullptr;
+    zb_opts opts{};
+    int nstreams = 4, depth = 2;
+    int64_t slice_req = 0;   // 0: from the kernel's capacity
+    size_t max_pending = 1024;
+
+    char *arena_base = nullptr;
+    Arena arena;
+    std::vector<hipStream_t> streams;
+    hipStream_t copy = nullptr;
+    unsigned long long *queues = nullptr;   // nstreams * depth blocks of MAXSEG
+    unsigned long long *nfail = nullptr;
+    std::vector<int> free_qblocks;
+    std::vector<hipEvent_t> free_events;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::thread worker;
+    bool stop = false;
+    zb_err broken = ZB_OK;
+    std::string broken_msg;
+
+    uint64_t next_ticket = 1;
+    std::deque<Request *> pending;
+    std::vector<Request *> active;          // admitted, not all zones launched or finished
+    std::map<uint64_t, Request *> all;       // every request not yet fetched
+    std::vector<Launch> inflight;
+    std::vector<int> per_stream;
+
+    // totals
+    uint64_t n_launches = 0, n_done = 0;
+    int64_t zones_done = 0;
+    size_t peak_used = 0;
+};
+
+static int64_t slice_zones(zb_server *S, const KernelInfo *k, int nr)
+{
+    if (S->slice_req > 0) return S->slice_req;
+    int per_cu = blocks_per_cu(k, nr);
+    int64_t cap = (int64_t)std::max(per_cu, 1) * S->ctx->cus * (64 / k->lanes);
+    // half a GPU of zones per slice: two slices per launch fill every slot, and a
+    // launch ends (freeing its stream for newer requests) after about two zone times
+    return std::max<int64_t>(cap / 2, 64);
+}
+
+static void fail_all(zb_server *S, zb_err e, const std::string &msg)
+{
+    S->broken = e;
+    S->broken_msg = msg;
+    for (auto &kv : S->all) {
+        if (kv.second->st != DONE) {
+            kv.second->st = DONE;
+            kv.second->t_done = now_s();
+        }
+    }
+    S->pending.clear();
+    S->active.clear();
+    S->cv_done.notify_all();
+}
+
+// One pass of the scheduler; called with S->mu held.  Returns true if anything happened.
+static bool schedule_once(zb_server *S, std::unique_lock<std::mutex> &lk)
+{
+    bool any = false;
+    // 1. completions
+    for (size_t i = 0; i < S->inflight.size();) {
+        Launch &L = S->inflight[i];
+        hipError_t q = hipEventQuery(L.done);
+        if (q == hipErrorNotReady) {
+            ++i;
+            continue;
+        }
+        if (q != hipSuccess) {
+            fail_all(S, ZB_EDEVICE, std::string("burn launch failed: ") + hipGetErrorString(q));
+            return true;
+        }
+        const double t = now_s();
+        for (auto &p : L.parts) {
+            Request *r = p.first;
+            r->finished += p.second;
+            if (r->finished == r->zones) {
+                r->st = DONE;
+                r->t_done = t;
+                S->n_done++;
+                S->zones_done += r->zones;
+                S->active.erase(std::find(S->active.begin(), S->active.end(), r));
+                S->cv_done.notify_all();
+            }
+        }
+        S->per_stream[L.stream]--;
+        S->free_qblocks.push_back(L.qblock);
+        S->free_events.push_back(L.done);
+        S->inflight.erase(S->inflight.begin() + i);
+        any = true;
+    }
+    // 2. admission, first come first served
+    while (!S->pending.empty()) {
+        Request *r = S->pending.front();
+        size_t off = 0;
+        if (!S->arena.alloc(r->bytes, &off)) break;
+        S->pending.pop_front();
+        r->off = off;
+        char *base = S->arena_base + off;
+        const int64_t z = r->zones;
+        size_t o = 0;
+        r->state = (double *)(base + o);
+        o += (sizeof(double) * r->row * z + ALIGN - 1) & ~(ALIGN - 1);
+        r->status = (int32_t *)(base + o);
+        o += (sizeof(int32_t) * z + ALIGN - 1) & ~(ALIGN - 1);
+        r->stats = (zb_zone_stats *)(base + o);
+        o += (sizeof(zb_zone_stats) * z + ALIGN - 1) & ~(ALIGN - 1);
+        r->scale = r->in_scale.empty() ? nullptr : (double *)(base + o);
+        S->peak_used = std::max(S->peak_used, S->arena.used());
+        // the upload runs outside the lock (pageable source); the request is not
+        // visible to the launcher until it is queued
+        lk.unlock();
+        hipError_t e1 = hipMemcpyAsync(r->state, r->in_state.data(), sizeof(double) * r->row * z,
+                                       hipMemcpyHostToDevice, S->copy);
+        hipError_t e2 = r->scale ? hipMemcpyAsync(r->scale, r->in_scale.data(), r->in_scale.size() * sizeof(double),
+                                                  hipMemcpyHostToDevice, S->copy)
+                                 : hipSuccess;
+        hipError_t e3 = hipEventRecord(r->uploaded, S->copy);
+        lk.lock();
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+            fail_all(S, ZB_EDEVICE, "upload of a request failed");
+            return true;
+        }
+        r->st = ADMITTED;
+        r->t_admit = now_s();
+        S->active.push_back(r);
+        any = true;
+    }
+    // 3. launches: fill every stream up to `depth` launches in flight
+    for (int s = 0; s < S->nstreams; ++s) {
+        while (S->per_stream[s] < S->depth) {
+            // the oldest request with zones left decides the kernel class
+            Request *head = nullptr;
+            for (Request *r : S->active)
+                if (r->next < r->zones) { head = r; break; }
+            if (!head) return any;
+            const KernelInfo *k = head->k;
+            std::vector<zb_segment> segs;
+            Launch L;
+            int max_nr = 0;
+            for (Request *r : S->active) {
+                if (r->k != k || r->next >= r->zones) continue;
+                max_nr = std::max(max_nr, r->net->dn.nr);
+            }
+            const int64_t slice = slice_zones(S, k, max_nr);
+            const int64_t cap = 2 * slice;
+            int64_t total = 0;
+            for (Request *r : S->active) {
+                if ((int)segs.size() >= MAXSEG || total >= cap) break;
+                if (r->k != k || r->next >= r->zones) continue;
+                int64_t n = std::min({r->zones - r->next, slice, cap - total});
+                zb_segment g;
+                g.net = r->net;
+                g.state = r->state + (size_t)r->next * r->row;
+                g.zones = n;
+                g.dt = r->dt;
+                g.rtol = r->rtol;
+                g.atol = r->atol;
+                g.rate_scale = r->scale ? r->scale + (size_t)r->next * r->net->dn.nr : nullptr;
+                g.zone_status = r->status + r->next;
+                g.stats = r->stats + r->next;
+                segs.push_back(g);
+                L.parts.push_back({r, n});
+                r->next += n;
+                total += n;
+                if (r->t_first == 0) r->t_first = now_s();
+            }
+            hipStream_t st = S->streams[s];
+            for (auto &p : L.parts) {
+                if (hipStreamWaitEvent(st, p.first->uploaded, 0) != hipSuccess) {
+                    fail_all(S, ZB_EDEVICE, "stream wait failed");
+                    return true;
+                }
+            }
+            L.qblock = S->free_qblocks.back();
+            S->free_qblocks.pop_back();
+            L.done = S->free_events.back();
+            S->free_events.pop_back();
+            L.stream = s;
+            Workspace ws{S->queues + (size_t)L.qblock * MAXSEG, 1, S->nfail};
+            zb_opts o = S->opts;
+            zb_err e = burn_impl(S->ctx, segs.data(), (int)segs.size(), &o, st, k->lanes, nullptr, &ws);
+            if (e == ZB_OK && hipEventRecord(L.done, st) != hipSuccess) e = ZB_EDEVICE;
+            if (e != ZB_OK) {
+                fail_all(S, e, "burn launch could not be issued");
+                return true;
+            }
+            S->per_stream[s]++;
+            S->n_launches++;
+            S->inflight.push_back(std::move(L));
+            any = true;
+        }
+    }
+    return any;
+}
+
+static void server_loop(zb_server *S)
+{
+    (void)hipSetDevice(S->ctx->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    while (!S->stop) {
+        bool any = S->broken == ZB_OK ? schedule_once(S, lk) : false;
+        if (S->stop) break;
+        if (!any) {
+            // poll launches in flight often; sleep longer when idle
+            auto wait = S->inflight.empty() ? std::chrono::milliseconds(5) : std::chrono::milliseconds(0);
+            if (S->inflight.empty())
+                S->cv_work.wait_for(lk, wait);
+            else
+                S->cv_work.wait_for(lk, std::chrono::microseconds(100));
+        }
+    }
+}
+
+static zb_err server_free(zb_server *S)
+{
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+    }
+    S->cv_work.notify_all();
+    if (S->worker.joinable()) S->worker.join();
+    DeviceGuard g(S->ctx->device);
+    for (auto s : S->streams) (void)hipStreamSynchronize(s);
+    if (S->copy) (void)hipStreamSynchronize(S->copy);
+    for (auto &kv : S->all) {
+        if (kv.second->uploaded) (void)hipEventDestroy(kv.second->uploaded);
+        delete kv.second;
+    }
+    for (auto &L : S->inflight) (void)hipEventDestroy(L.done);
+    for (auto e : S->free_events) (void)hipEventDestroy(e);
+    for (auto s : S->streams) (void)hipStreamDestroy(s);
+    if (S->copy) (void)hipStreamDestroy(S->copy);
+    if (S->arena_base) (void)hipFree(S->arena_base);
+    if (S->queues) (void)hipFree(S->queues);
+    delete S;
+    return ZB_OK;
+}
+
+extern "C" zb_err zb_server_create(zb_context *ctx, const zb_server_opts *so, zb_server **out)
+{
+    if (!ctx || !so || !out) return fail(ZB_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (so->hbm_budget_bytes < (1u << 20)) return fail(ZB_EINVAL, "hbm_budget_bytes must be at least 1 MiB");
+    if (so->streams < 0 || so->streams > 8) return fail(ZB_EINVAL, "streams must be 0..8");
+    if (so->launches_per_stream < 0 || so->launches_per_stream > 4)
+        return fail(ZB_EINVAL, "launches_per_stream must be 0..4");
+    if (so->slice_zones < 0 || so->max_pending < 0) return fail(ZB_EINVAL, "negative size");
+    const zb_opts &bo = so->burn;
+    if (bo.precision != ZB_FP64 && bo.precision != ZB_MIXED) return fail(ZB_EINVAL, "precision %d", bo.precision);
+    if (bo.mapping != ZB_MAP_AUTO && (bo.mapping < 1 || bo.mapping > 64 || (bo.mapping & (bo.mapping - 1))))
+        return fail(ZB_EINVAL, "mapping must be 0 or a power of two 1..64");
+    DeviceGuard g(ctx->device);
+    zb_server *S = new (std::nothrow) zb_server();
+    if (!S) return fail(ZB_ENOMEM, "host allocation failed");
+    S->ctx = ctx;
+    S->opts = bo;
+    S->nstreams = so->streams ? so->streams : 4;
+    S->depth = so->launches_per_stream ? so->launches_per_stream : 2;
+    S->slice_req = so->slice_zones;
+    S->max_pending = so->max_pending ? (size_t)so->max_pending : 1024;
+    const int nblocks = S->nstreams * S->depth;
+    if (hipMalloc((void **)&S->arena_base, so->hbm_budget_bytes) != hipSuccess) {
+        delete S;
+        return fail(ZB_ENOMEM, "could not allocate the HBM budget of %zu bytes", (size_t)so->hbm_budget_bytes);
+    }
+    S->arena.init(so->hbm_budget_bytes);
+    if (hipMalloc((void **)&S->queues, sizeof(unsigned long long) * (MAXSEG * (size_t)nblocks + 1)) != hipSuccess) {
+        (void)hipFree(S->arena_base);
+        delete S;
+        return fail(ZB_ENOMEM, "queue allocation failed");
+    }
+    S->nfail = S->queues + (size_t)MAXSEG * nblocks;
+    S->streams.resize(S->nstreams, nullptr);
+    S->per_stream.assign(S->nstreams, 0);
+    bool ok = launch_reset(S->nfail, 1, nullptr) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+    for (int i = 0; ok && i < S->nstreams; ++i) ok = hipStreamCreateWithFlags(&S->streams[i], hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&S->copy, hipStreamNonBlocking) == hipSuccess;
+    for (int i = 0; ok && i < nblocks; ++i) {
+        hipEvent_t e = nullptr;
+        ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+        if (ok) S->free_events.push_back(e);
+        S->free_qblocks.push_back(i);
+    }
+    if (!ok) {
+        server_free(S);
+        return fail(ZB_EDEVICE, "stream or event creation failed");
+    }
+    S->worker = std::thread(server_loop, S);
+    *out = S;
+    return ZB_OK;
+}
+
+extern "C" zb_err zb_server_submit(zb_server *S, const zb_network *net, const double *host_state,
+                                   int64_t zones, double dt, double rtol, double atol,
+                                   const double *host_rate_scale, uint64_t *ticket)
+{
+    if (!S || !net || !ticket) return fail(ZB_EINVAL, "NULL argument");
+    if (net->ctx != S->ctx) return fail(ZB_EINVAL, "network belongs to another context");
+    if (zones <= 0 || !host_state) return fail(ZB_EINVAL, "a request needs zones > 0 and a state");
+    if (!(isfinite(dt) && dt > 0.0) || !(isfinite(rtol) && rtol > 0.0) || !(isfinite(atol) && atol > 0.0))
+        return fail(ZB_EINVAL, "dt, rtol and atol must be finite and > 0");
+    const int row = net->dn.ns + 1;
+    const int lanes = lanes_for(S->ctx, net, S->opts.precision, &S->opts);
+    const KernelInfo *k = find_kernel(net->dn.nv, lanes, S->opts.precision == ZB_MIXED);
+    if (!k) return fail(ZB_EUNSUPPORTED, "no kernel for nv=%d with %d lanes", net->dn.nv, lanes);
+    auto al = [](size_t b) { return (b + ALIGN - 1) & ~(ALIGN - 1); };
+    size_t bytes = al(sizeof(double) * row * (size_t)zones) + al(sizeof(int32_t) * (size_t)zones) +
+                   al(sizeof(zb_zone_stats) * (size_t)zones) +
+                   (host_rate_scale ? al(sizeof(double) * net->dn.nr * (size_t)zones) : 0);
+    if (bytes > S->arena.size())
+        return fail(ZB_EINVAL, "request needs %zu device bytes, more than the whole budget", bytes);
+    Request *r = new (std::nothrow) Request();
+    if (!r) return fail(ZB_ENOMEM, "host allocation failed");
+    r->net = net;
+    r->k = k;
+    r->row = row;
+    r->zones = zones;
+    r->dt = dt;
+    r->rtol = rtol;
+    r->atol = atol;
+    r->bytes = bytes;
+    r->t_submit = now_s();
+    try {
+        r->in_state.assign(host_state, host_state + (size_t)row * zones);
+        if (host_rate_scale) r->in_scale.assign(host_rate_scale, host_rate_scale + (size_t)net->dn.nr * zones);
+    } catch (...) {
+        delete r;
+        return fail(ZB_ENOMEM, "host copy of the request failed");
+    }
+    {
+        DeviceGuard g(S->ctx->device);
+        if (hipEventCreateWithFlags(&r->uploaded, hipEventDisableTiming) != hipSuccess) {
+            delete r;
+            return fail(ZB_EDEVICE, "event creation failed");
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->broken != ZB_OK) {
+            (void)hipEventDestroy(r->uploaded);
+            delete r;
+            return fail(S->broken, "server stopped: %s", S->broken_msg.c_str());
+        }
+        if (S->pending.size() >= S->max_pending) {
+            (void)hipEventDestroy(r->uploaded);
+            delete r;
+            return fail(ZB_EBUSY, "pending queue full (%zu requests)", S->max_pending);
+        }
+        r->ticket = S->next_ticket++;
+        S->pending.push_back(r);
+        S->all[r->ticket] = r;
+        *ticket = r->ticket;
+    }
+    S->cv_work.notify_all();
+    return ZB_OK;
+}
+
+extern "C" zb_err zb_server_wait(zb_server *S, uint64_t ticket, double timeout_s, int32_t *done)
+{
+    if (!S || !done) return fail(ZB_EINVAL, "NULL argument");
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return fail(ZB_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+    Request *r = it->second;
+    if (timeout_s > 0.0)
+        S->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), [&] { return r->st == DONE; });
+    *done = r->st == DONE;
+    if (S->broken != ZB_OK) return fail(S->broken, "server stopped: %s", S->broken_msg.c_str());
+    return ZB_OK;
+}
+
+extern "C" zb_err zb_server_fetch(zb_server *S, uint64_t ticket, double *host_state_out,
+                                  int32_t *zone_status_out, zb_zone_stats *stats_out,
+                                  zb_request_info *info)
+{
+    if (!S) return fail(ZB_EINVAL, "NULL server");
+    Request *r = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->all.find(ticket);
+        if (it == S->all.end()) return fail(ZB_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+        r = it->second;
+        if (S->broken != ZB_OK) return fail(S->broken, "server stopped: %s", S->broken_msg.c_str());
+        if (r->st != DONE) return fail(ZB_EBUSY, "request %llu is not finished", (unsigned long long)ticket);
+        S->all.erase(it);
+    }
+    DeviceGuard g(S->ctx->device);
+    const int64_t z = r->zones;
+    zb_err e = ZB_OK;
+    std::vector<int32_t> st;
+    int32_t *st_dst = zone_status_out;
+    if (info && !st_dst) {
+        st.resize(z);
+        st_dst = st.data();
+    }
+    if (host_state_out &&
+        hipMemcpyAsync(host_state_out, r->state, sizeof(double) * r->row * z, hipMemcpyDeviceToHost, S->copy) != hipSuccess)
+        e = ZB_EDEVICE;
+    if (e == ZB_OK && st_dst &&
+        hipMemcpyAsync(st_dst, r->status, sizeof(int32_t) * z, hipMemcpyDeviceToHost, S->copy) != hipSuccess)
+        e = ZB_EDEVICE;
+    if (e == ZB_OK && stats_out &&
+        hipMemcpyAsync(stats_out, r->stats, sizeof(zb_zone_stats) * z, hipMemcpyDeviceToHost, S->copy) != hipSuccess)
+        e = ZB_EDEVICE;
+    if (e == ZB_OK && hipStreamSynchronize(S->copy) != hipSuccess) e = ZB_EDEVICE;
+    if (info) {
+        info->zones = z;
+        int64_t ok = 0;
+        if (e == ZB_OK)
+            for (int64_t i = 0; i < z; ++i) ok += st_dst[i] == ZB_ZONE_OK;
+        info->zones_ok = ok;
+        info->queue_s = r->t_admit - r->t_submit;
+        info->latency_s = r->t_done - r->t_submit;
+        info->first_launch_s = r->t_first - r->t_submit;
+    }
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->arena.release(r->off, r->bytes);
+    }
+    S->cv_work.notify_all();   // memory freed: admission may proceed
+    (void)hipEventDestroy(r->uploaded);
+    delete r;
+    return e == ZB_OK ? ZB_OK : fail(e, "copy of the results failed");
+}
+
+extern "C" zb_err zb_server_stats(zb_server *S, zb_server_totals *out)
+{
+    if (!S || !out) return fail(ZB_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    out->requests_done = (int64_t)S->n_done;
+    out->zones_done = S->zones_done;
+    out->launches = (int64_t)S->n_launches;
+    out->pending = (int64_t)S->pending.size();
+    out->active = (int64_t)S->active.size();
+    out->bytes_in_use = (int64_t)S->arena.used();
+    out->peak_bytes_in_use = (int64_t)S->peak_used;
+    return ZB_OK;
+}
+
+extern "C" zb_err zb_server_destroy(zb_server *S)
+{
+    if (!S) return ZB_OK;
+    return server_free(S);
+}

@@ -221,3 +221,14 @@ def serving_requests(n_requests, seed=501, rate_hz=100.0, size_range=(1 << 10, 1
     zseeds = rng.integers(0, 2**31 - 1, size=n_requests)
     return [dict(arrival=float(arrivals[i]), net=int(netidx[i]), zones=int(sizes[i]),
                  rtol=float(rt[i]), seed=int(zseeds[i])) for i in range(n_requests)]
+
+
+def request_inputs(nets, req):
+    """(state, rate scales or None, dt) of one request drawn by serving_requests(); nets are
+    config3_networks() (0 Robertson, 1..3 the random networks of 14, 22, 48 variables)."""
+    k = req["net"]
+    if k == 0:
+        st, sc = robertson_zones(req["zones"], seed=req["seed"])
+        return st, sc, 1.0e5
+    st = random_zones(nets[k], req["zones"], req["seed"], T_range=CONFIG3_T_RANGE, T_dist="loguniform")
+    return st, None, 1.0

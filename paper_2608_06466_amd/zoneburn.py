@@ -46,6 +46,22 @@ class _Segment(C.Structure):
                 ("rate_scale", C.c_void_p), ("zone_status", C.c_void_p), ("stats", C.c_void_p)]
 
 
+class _ServerOpts(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("streams", C.c_int32),
+                ("launches_per_stream", C.c_int32), ("slice_zones", C.c_int64),
+                ("max_pending", C.c_int32), ("reserved", C.c_int32), ("burn", _Opts)]
+
+
+class _ReqInfo(C.Structure):
+    _fields_ = [("zones", C.c_int64), ("zones_ok", C.c_int64), ("queue_s", C.c_double),
+                ("first_launch_s", C.c_double), ("latency_s", C.c_double)]
+
+
+class _Totals(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("requests_done", "zones_done", "launches", "pending",
+                                        "active", "bytes_in_use", "peak_bytes_in_use")]
+
+
 _lib = None
 
 
@@ -69,6 +85,15 @@ def lib():
             "zb_burn_batch": [p, C.POINTER(_Segment), i32, C.POINTER(_Opts), p],
             "zb_get_mapping": [p, p, i32, C.POINTER(i32)],
             "zb_autotune": [p, p, p, i64, d, d, d, i32, C.POINTER(i32), C.POINTER(C.c_float)],
+            "zb_graph_create": [p, C.POINTER(_Segment), i32, C.POINTER(_Opts), C.POINTER(p)],
+            "zb_graph_launch": [p, p],
+            "zb_graph_destroy": [p],
+            "zb_server_create": [p, C.POINTER(_ServerOpts), C.POINTER(p)],
+            "zb_server_submit": [p, p, p, i64, d, d, d, p, C.POINTER(C.c_uint64)],
+            "zb_server_wait": [p, C.c_uint64, d, C.POINTER(i32)],
+            "zb_server_fetch": [p, C.c_uint64, p, p, p, C.POINTER(_ReqInfo)],
+            "zb_server_stats": [p, C.POINTER(_Totals)],
+            "zb_server_destroy": [p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -180,8 +205,7 @@ def burn(ctx, net, state, dt, rtol, atol, rate_scale=None, precision="fp64", lan
     return status, stats
 
 
-def burn_batch(ctx, segments, precision="fp64", lanes=0, max_steps=0, stream=None):
-    """segments: list of dicts(net, state, dt, rtol, atol, rate_scale=None, status=None, stats=None)."""
+def _segments(segments):
     arr = (_Segment * len(segments))()
     for i, s in enumerate(segments):
         _check_state(s["net"], s["state"])
@@ -190,9 +214,114 @@ def burn_batch(ctx, segments, precision="fp64", lanes=0, max_steps=0, stream=Non
                           _ptr(s.get("rate_scale")).value if s.get("rate_scale") is not None else None,
                           s["status"].data_ptr() if s.get("status") is not None else None,
                           s["stats"].data_ptr() if s.get("stats") is not None else None)
+    return arr
+
+
+def burn_batch(ctx, segments, precision="fp64", lanes=0, max_steps=0, stream=None):
+    """segments: list of dicts(net, state, dt, rtol, atol, rate_scale=None, status=None, stats=None)."""
+    arr = _segments(segments)
     o = _opts(precision, lanes, max_steps)
     _check(lib().zb_burn_batch(ctx.h, arr, len(segments), C.byref(o), _stream_handle(stream)),
            "zb_burn_batch")
+
+
+class Graph:
+    """A burn of fixed buffers captured once as a HIP graph (zb_graph_*); launch() replays it."""
+
+    def __init__(self, ctx, segments, precision="fp64", lanes=0, max_steps=0):
+        self.ctx = ctx
+        self._segs = segments          # the buffers must outlive the graph
+        arr = _segments(segments)
+        o = _opts(precision, lanes, max_steps)
+        h = C.c_void_p()
+        _check(lib().zb_graph_create(ctx.h, arr, len(segments), C.byref(o), C.byref(h)),
+               "zb_graph_create")
+        self.h = h
+
+    def launch(self, stream=None):
+        _check(lib().zb_graph_launch(self.h, _stream_handle(stream)), "zb_graph_launch")
+
+    def close(self):
+        if self.h:
+            lib().zb_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching burn server (zb_server_*): host inputs in, host results out."""
+
+    def __init__(self, ctx, hbm_budget_bytes, precision="fp64", lanes=0, max_steps=0, streams=0,
+                 launches_per_stream=0, slice_zones=0, max_pending=0):
+        self.ctx = ctx
+        o = _ServerOpts(int(hbm_budget_bytes), int(streams), int(launches_per_stream),
+                        int(slice_zones), int(max_pending), 0, _opts(precision, lanes, max_steps))
+        h = C.c_void_p()
+        _check(lib().zb_server_create(ctx.h, C.byref(o), C.byref(h)), "zb_server_create")
+        self.h = h
+        self._rows = {}
+
+    def submit(self, net, state, dt, rtol, atol, rate_scale=None):
+        """state: host float64 [zones][ns+1] (copied); returns a ticket."""
+        st = np.ascontiguousarray(state, dtype=np.float64)
+        if st.ndim != 2 or st.shape[1] != net.ns + 1:
+            raise ValueError("state must be [zones][ns+1]")
+        sc = None
+        if rate_scale is not None:
+            sc = np.ascontiguousarray(rate_scale, dtype=np.float64)
+            if sc.shape != (st.shape[0], net.nr):
+                raise ValueError("rate_scale must be [zones][n_reactions]")
+        t = C.c_uint64(0)
+        _check(lib().zb_server_submit(self.h, net.h, st.ctypes.data_as(C.c_void_p), st.shape[0],
+                                      float(dt), float(rtol), float(atol),
+                                      None if sc is None else sc.ctypes.data_as(C.c_void_p),
+                                      C.byref(t)), "zb_server_submit")
+        self._rows[t.value] = (st.shape[0], st.shape[1])
+        return t.value
+
+    def wait(self, ticket, timeout=0.0):
+        d = C.c_int32(0)
+        _check(lib().zb_server_wait(self.h, C.c_uint64(ticket), float(timeout), C.byref(d)),
+               "zb_server_wait")
+        return bool(d.value)
+
+    def fetch(self, ticket):
+        """(state, status, stats, info) of a finished request; releases it on the server."""
+        if ticket not in self._rows:   # unknown here: let the library report it
+            _check(lib().zb_server_fetch(self.h, C.c_uint64(ticket), None, None, None, None),
+                   "zb_server_fetch")
+        z, row = self._rows[ticket]
+        out = np.empty((z, row), dtype=np.float64)
+        status = np.empty(z, dtype=np.int32)
+        stats = np.empty((z, 7), dtype=np.int32)
+        info = _ReqInfo()
+        _check(lib().zb_server_fetch(self.h, C.c_uint64(ticket), out.ctypes.data_as(C.c_void_p),
+                                     status.ctypes.data_as(C.c_void_p),
+                                     stats.ctypes.data_as(C.c_void_p), C.byref(info)),
+               "zb_server_fetch")
+        del self._rows[ticket]
+        return out, status, stats, {k: getattr(info, k) for k, _ in _ReqInfo._fields_}
+
+    def stats(self):
+        t = _Totals()
+        _check(lib().zb_server_stats(self.h, C.byref(t)), "zb_server_stats")
+        return {k: getattr(t, k) for k, _ in _Totals._fields_}
+
+    def close(self):
+        if self.h:
+            lib().zb_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def sync(ctx, stream=None):

@@ -50,3 +50,33 @@ def test_workload_generators_are_deterministic():
     assert 2 * np.log(10) <= net["lnA"].min() and net["lnA"].max() <= 10 * np.log(10)
     s, sc = W.robertson_zones(16)
     assert np.all(s[:, 0] == 1.0) and sc.shape == (16, 3)
+
+
+def test_struct_layouts_match_the_binding(tmp_path):
+    """sizeof/offsetof of every ABI struct, compiled from the header, equal the ctypes layouts."""
+    import ctypes
+    import shutil
+    import subprocess
+    from paper_2608_06466_amd import zoneburn as zb
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    structs = {"zb_server_opts": zb._ServerOpts, "zb_request_info": zb._ReqInfo,
+               "zb_server_totals": zb._Totals, "zb_segment": zb._Segment, "zb_opts": zb._Opts,
+               "zb_network_desc": zb._Desc}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "zoneburn.h"', "int main(void){"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([gcc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                   text=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)

@@ -1,0 +1,202 @@
+"""GPU tests of the runtime around the burn kernels: multi-class batches, HIP-graph replays,
+and the continuous-batching server.  Results are compared bitwise with plain zb_burn calls,
+whose parity with the oracle is covered in test_gpu_parity.py."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2608_06466_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def zbm():
+    from paper_2608_06466_amd import zoneburn as zb
+    assert torch.cuda.is_available()
+    ctx = zb.Context(0)
+    nets_d = W.config3_networks()
+    nets = [zb.Network(ctx, n) for n in nets_d]
+    yield zb, ctx, nets_d, nets
+    for n in nets:
+        n.close()
+    ctx.close()
+
+
+def inputs(k, nets_d, zones, seed):
+    """State (and rate scales) of config-3 network k: 0 Robertson, 1..3 random nv 14/22/48."""
+    if k == 0:
+        st, sc = W.robertson_zones(zones, seed=seed)
+        return st, sc, 1.0e5
+    st = W.random_zones(nets_d[k], zones, seed=seed, T_range=W.CONFIG3_T_RANGE, T_dist="loguniform")
+    return st, None, 1.0
+
+
+def burn_alone(zb, ctx, net, st, sc, dt, rtol, precision):
+    t = torch.tensor(st, device="cuda:0")
+    s = None if sc is None else torch.tensor(sc, device="cuda:0")
+    status, stats = zb.burn(ctx, net, t, dt, rtol, 1e-12, rate_scale=s, precision=precision)
+    zb.sync(ctx)
+    return t.cpu().numpy(), status.cpu().numpy(), stats.cpu().numpy()
+
+
+def make_segments(zb, nets_d, nets, sizes, seed=11):
+    segs, host = [], []
+    for k, nz in enumerate(sizes):
+        st, sc, dt = inputs(k, nets_d, nz, seed + k)
+        seg = dict(net=nets[k], state=torch.tensor(st, device="cuda:0"), dt=dt, rtol=1e-8, atol=1e-12,
+                   rate_scale=None if sc is None else torch.tensor(sc, device="cuda:0"),
+                   status=torch.empty(nz, dtype=torch.int32, device="cuda:0"),
+                   stats=torch.empty((nz, 7), dtype=torch.int32, device="cuda:0"))
+        segs.append(seg)
+        host.append((st, sc, dt))
+    return segs, host
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_four_kernel_classes_in_one_call_match_single_burns(zbm, precision):
+    """Robertson, nv 14, 22 and 48 in one zb_burn_batch call (concurrent launches on forked
+    streams): bitwise the single-network results."""
+    zb, ctx, nets_d, nets = zbm
+    segs, host = make_segments(zb, nets_d, nets, [700, 300, 130, 65])
+    zb.burn_batch(ctx, segs, precision=precision)
+    zb.sync(ctx)
+    for k, seg in enumerate(segs):
+        st, sc, dt = host[k]
+        ref = burn_alone(zb, ctx, nets[k], st, sc, dt, 1e-8, precision)
+        assert np.array_equal(seg["state"].cpu().numpy(), ref[0]), k
+        assert np.array_equal(seg["status"].cpu().numpy(), ref[1]), k
+        assert np.array_equal(seg["stats"].cpu().numpy(), ref[2]), k
+
+
+def test_graph_replays_match_eager(zbm):
+    """A captured four-class burn replayed three times, with eager burns in between, gives the
+    eager result every time."""
+    zb, ctx, nets_d, nets = zbm
+    segs, host = make_segments(zb, nets_d, nets, [500, 200, 90, 40], seed=31)
+    init = [s["state"].clone() for s in segs]
+    zb.burn_batch(ctx, segs, precision="mixed")
+    zb.sync(ctx)
+    eager = [(s["state"].cpu().numpy(), s["status"].cpu().numpy(), s["stats"].cpu().numpy()) for s in segs]
+    g = zb.Graph(ctx, segs, precision="mixed")
+    other = torch.tensor(W.config2(128)["state"], device="cuda:0")
+    other0 = other.clone()
+    net2 = zb.Network(ctx, W.config2_network())
+    for rep in range(3):
+        for s, i0 in zip(segs, init):
+            s["state"].copy_(i0)
+            s["status"].fill_(-1)
+        torch.cuda.synchronize()
+        g.launch()
+        zb.sync(ctx)
+        for k, s in enumerate(segs):
+            assert np.array_equal(s["state"].cpu().numpy(), eager[k][0]), (rep, k)
+            assert np.array_equal(s["status"].cpu().numpy(), eager[k][1]), (rep, k)
+            assert np.array_equal(s["stats"].cpu().numpy(), eager[k][2]), (rep, k)
+        # unrelated eager work between replays
+        other.copy_(other0)
+        zb.burn(ctx, net2, other, 1.0, 1e-8, 1e-12)
+        zb.sync(ctx)
+    g.close()
+    net2.close()
+
+
+def test_torch_graph_capture_of_zb_burn(zbm):
+    """zb.burn captured by torch.cuda.graph (the kernels clear their queues with a kernel, not a
+    memset node) and replayed with the state reset eagerly in between."""
+    zb, ctx, nets_d, nets = zbm
+    c = W.config2(256)
+    net = zb.Network(ctx, c["net"])
+    ref = burn_alone(zb, ctx, net, c["state"], None, 1.0, 1e-8, "fp64")
+    static = torch.tensor(c["state"], device="cuda:0")
+    init = static.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):   # warm-up outside the capture
+        zb.burn(ctx, net, static, 1.0, 1e-8, 1e-12)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        status, stats = zb.burn(ctx, net, static, 1.0, 1e-8, 1e-12)
+    for rep in range(3):
+        static.copy_(init)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(static.cpu().numpy(), ref[0]), rep
+        assert np.array_equal(status.cpu().numpy(), ref[1]), rep
+        assert np.array_equal(stats.cpu().numpy(), ref[2]), rep
+    zb.sync(ctx)
+    net.close()
+
+
+def serving_mix(nets_d, n, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n):
+        k = int(rng.integers(0, 4))
+        zones = int(np.rint(np.exp(rng.uniform(np.log(64), np.log([3000, 1500, 600, 150][k])))))
+        rtol = float(rng.choice([1e-6, 1e-8]))
+        st, sc, dt = inputs(k, nets_d, zones, 1000 + i)
+        reqs.append(dict(k=k, zones=zones, rtol=rtol, state=st, scale=sc, dt=dt))
+    return reqs
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_server_results_same_alone_and_in_the_mix(zbm, precision):
+    """Requests of all four networks, two tolerances and many sizes, submitted while earlier
+    ones run: each result is bitwise the result of the same request burned alone."""
+    zb, ctx, nets_d, nets = zbm
+    reqs = serving_mix(nets_d, 16, seed=5)
+    srv = zb.Server(ctx, 256 << 20, precision=precision, slice_zones=97)
+    tickets = []
+    for i, r in enumerate(reqs):
+        tickets.append(srv.submit(nets[r["k"]], r["state"], r["dt"], r["rtol"], 1e-12, r["scale"]))
+        if i % 4 == 3:
+            time.sleep(0.002)   # later requests arrive while earlier ones are on the GPU
+    results = []
+    for t in tickets:
+        assert srv.wait(t, timeout=120.0)
+        results.append(srv.fetch(t))
+    tot = srv.stats()
+    srv.close()
+    assert tot["requests_done"] == len(reqs) and tot["bytes_in_use"] == 0
+    assert tot["launches"] < sum(-(-r["zones"] // 97) for r in reqs)   # slices shared launches
+    for r, (out, status, stats, info) in zip(reqs, results):
+        ref = burn_alone(zb, ctx, nets[r["k"]], r["state"], r["scale"], r["dt"], r["rtol"], precision)
+        assert np.array_equal(out, ref[0])
+        assert np.array_equal(status, ref[1])
+        assert np.array_equal(stats, ref[2])
+        assert info["zones"] == r["zones"] and info["zones_ok"] == int((ref[1] == 0).sum())
+        assert 0.0 <= info["queue_s"] <= info["first_launch_s"] <= info["latency_s"]
+
+
+def test_server_admission_waits_for_memory(zbm):
+    """A budget that holds about two requests at a time: every request still completes, resident
+    bytes never exceed the budget, and the queue of waiting requests is bounded."""
+    zb, ctx, nets_d, nets = zbm
+    budget = 1 << 20
+    st, sc, dt = inputs(1, nets_d, 2500, 77)       # 2500 zones x (112 + 4 + 28) B = 360 KB
+    srv = zb.Server(ctx, budget, max_pending=4)
+    tickets = [srv.submit(nets[1], st, dt, 1e-8, 1e-12) for _ in range(4)]
+    with pytest.raises(zb.ZoneburnError) as e:
+        for _ in range(8):            # the pending queue (4) fills before the first admissions
+            tickets.append(srv.submit(nets[1], st, dt, 1e-8, 1e-12))
+    assert e.value.code in (zb.EBUSY,)
+    with pytest.raises(zb.ZoneburnError) as e2:
+        srv.submit(nets[1], np.tile(st, (4, 1)), dt, 1e-8, 1e-12)   # larger than the budget
+    assert e2.value.code == zb.EINVAL
+    ref = burn_alone(zb, ctx, nets[1], st, None, dt, 1e-8, "fp64")
+    for t in tickets:
+        assert srv.wait(t, timeout=120.0)
+        out, status, stats, info = srv.fetch(t)
+        assert np.array_equal(out, ref[0]) and np.array_equal(status, ref[1])
+    tot = srv.stats()
+    assert 0 < tot["peak_bytes_in_use"] <= budget
+    with pytest.raises(zb.ZoneburnError) as e3:
+        srv.fetch(tickets[0])
+    assert e3.value.code == zb.ENOTFOUND
+    srv.close()
