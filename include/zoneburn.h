@@ -156,8 +156,9 @@ zb_err zb_graph_destroy(zb_graph *graph);
    fits in the server's HBM budget, which is allocated once at creation (no device allocation
    per request).  A scheduler thread cuts admitted requests into slices of zones and keeps
    persistent launches in flight on several streams; a launch holds slices of up to 8
-   requests that use the same kernel class, and a request arriving while others run joins the
-   next launch, its kernels overlapping the launches in flight.  Results stay in device memory
+   requests that use the same kernel class, taken shortest remaining work first (estimated
+   from zones left and the network's size), and a request arriving while others run joins
+   the next launch, its kernels overlapping the launches in flight.  Results stay in device memory
    until zb_server_fetch copies them out and frees the memory.  Every zone is burned exactly
    (bitwise) as zb_burn would burn it with opts = zb_server_opts.burn, so a request's result
    is the same alone and in any mix.  Latencies are measured on the host from submit.

@@ -6,7 +6,8 @@
 // the request path).  Admitted requests are cut into slices of zones; a
 // scheduler thread keeps a few persistent launches in flight on several
 // streams, each launch holding up to MAXSEG slices of requests that use the
-// same kernel class (any network or tolerance of that class).  Requests that
+// same kernel class (any network or tolerance of that class), taken
+// shortest-remaining-work first.  Requests that
 // arrive while others run join the next launch, and their kernels overlap the
 // ones in flight (a launch's tail is filled by the next).  Results stay in
 // device memory until fetched.  A zone's result depends only on its own input
@@ -104,6 +105,7 @@ struct Request {
     int32_t *status = nullptr;
     zb_zone_stats *stats = nullptr;
     hipEvent_t uploaded = nullptr;
+    double cost = 1.0;       // relative device work per zone (see zb_server_submit)
     int64_t next = 0;        // first zone not yet in a launch
     int64_t finished = 0;    // zones whose launch has completed
     ReqState st = PENDING;
@@ -255,25 +257,30 @@ static bool schedule_once(zb_server *S, std::unique_lock<std::mutex> &lk)
     // 3. launches: fill every stream up to `depth` launches in flight
     for (int s = 0; s < S->nstreams; ++s) {
         while (S->per_stream[s] < S->depth) {
-            // the oldest request with zones left decides the kernel class
-            Request *head = nullptr;
+            // Shortest remaining work first: the request with the least estimated
+            // work left decides the kernel class, and the launch takes slices of the
+            // requests of that class in the same order.  New small requests thus pass
+            // large ones at launch granularity (mean and median latency), while a large
+            // request still gets every launch slot nobody else needs.
+            std::vector<Request *> cand;
             for (Request *r : S->active)
-                if (r->next < r->zones) { head = r; break; }
-            if (!head) return any;
-            const KernelInfo *k = head->k;
-            std::vector<zb_segment> segs;
-            Launch L;
+                if (r->next < r->zones) cand.push_back(r);
+            if (cand.empty()) return any;
+            auto left = [](const Request *r) { return (double)(r->zones - r->next) * r->cost; };
+            std::stable_sort(cand.begin(), cand.end(),
+                             [&](const Request *a, const Request *b) { return left(a) < left(b); });
+            const KernelInfo *k = cand[0]->k;
             int max_nr = 0;
-            for (Request *r : S->active) {
-                if (r->k != k || r->next >= r->zones) continue;
-                max_nr = std::max(max_nr, r->net->dn.nr);
-            }
+            for (Request *r : cand)
+                if (r->k == k) max_nr = std::max(max_nr, r->net->dn.nr);
             const int64_t slice = slice_zones(S, k, max_nr);
             const int64_t cap = 2 * slice;
+            std::vector<zb_segment> segs;
+            Launch L;
             int64_t total = 0;
-            for (Request *r : S->active) {
+            for (Request *r : cand) {
                 if ((int)segs.size() >= MAXSEG || total >= cap) break;
-                if (r->k != k || r->next >= r->zones) continue;
+                if (r->k != k) continue;
                 int64_t n = std::min({r->zones - r->next, slice, cap - total});
                 zb_segment g;
                 g.net = r->net;
@@ -446,6 +453,9 @@ extern "C" zb_err zb_server_submit(zb_server *S, const zb_network *net, const do
     r->rtol = rtol;
     r->atol = atol;
     r->bytes = bytes;
+    // relative work per zone for the launch order: per step the LU and solves grow
+    // with the square of the padded size, the rates and Jacobian with the reactions
+    r->cost = (double)k->nvp * k->nvp * (double)(net->dn.nr + net->dn.nv);
     r->t_submit = now_s();
     try {
         r->in_state.assign(host_state, host_state + (size_t)row * zones);
