@@ -83,6 +83,11 @@ __device__ __forceinline__ float opq(float v) { asm volatile("" : "+v"(v)); retu
 template <class D>
 __device__ __forceinline__ int after(int v, D d) { asm volatile("" : "+v"(v) : "v"(d)); return v; }
 
+// A wave-uniform integer made to depend on d (no instruction): bounds how far the
+// scheduler can hoist scalar reads that use it.
+template <class D>
+__device__ __forceinline__ int after_s(int v, D d) { asm volatile("" : "+s"(v) : "v"(d)); return v; }
+
 // A private copy of a wave-uniform integer (no instruction).  Comparisons of
 // the LU and solve loops against the network size are then not shared between
 // those routines, which would keep one scalar mask per column live across a
@@ -227,6 +232,20 @@ template <int L, int K>
 __device__ __forceinline__ float bcast_k(float v)
 {
     return __uint_as_float(bcast_k32<L, K>(__float_as_uint(v)));
+}
+
+// Value of lane src (wave-uniform) of the wave, with v_readlane.
+__device__ __forceinline__ double lane_read(double v, int src)
+{
+    unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(u & 0xffffffffu), src);
+    unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), src);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ float lane_read(float v, int src)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 
 // Value of lane src of the wave (ds_bpermute; no LDS memory is touched).
@@ -480,36 +499,49 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
         int i = row_of<NVP, L>(c, s);
         double fi = 0.0;
         if (i < N.ns) {
-            const int *lst = N.inv + i * N.inv_len;
+            // two list entries per iteration (one 16-byte load), contributions added
+            // in list order; each entry carries the reactant columns it feeds
+            const int4 *lst = (const int4 *)(N.inv + i * N.inv_len);
             double jit = 0.0;
             double *jrow = jb + i * JS;
-            for (int e = 0; e < N.inv_len; ++e) {
-                int en = lst[e];
-                if (en < 0) break;
-                int r = en & 0xffff;
-                double nu = (double)((en >> 16) - 8);
+            auto entry = [&](int x, int y) {
+                const int r = x & 0xffff;
+                const double nu = (double)((x >> 16) - 8);
                 fi = fma(nu, rx[r], fi);
                 if (WANTJ) {
-                    int2 ab = *(const int2 *)&N.rct[r];
-                    __hip_atomic_fetch_add(jrow + ab.x, nu * rx[nr + r], __ATOMIC_RELAXED,
+                    const int a = y & 0xff, b = (y >> 8) - 1;
+                    __hip_atomic_fetch_add(jrow + a, nu * rx[nr + r], __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
-                    if (ab.y >= 0)
-                        __hip_atomic_fetch_add(jrow + ab.y, nu * rx[2 * nr + r], __ATOMIC_RELAXED,
+                    if (b >= 0)
+                        __hip_atomic_fetch_add(jrow + b, nu * rx[2 * nr + r], __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_WORKGROUP);
                     jit = fma(nu, rx[3 * nr + r], jit);
                 }
+            };
+            for (int e = 0; e < N.inv_len / 2; ++e) {
+                const int4 en = lst[e];
+                if (en.x < 0) break;
+                entry(en.x, en.y);
+                if (en.z < 0) break;
+                entry(en.z, en.w);
             }
             if (WANTJ && N.thermal) {
                 jrow[N.ns] = jit;
-                const int *rl = N.rea + i * N.rea_len;
+                // T row: sum over the reactions that consume species i of q_r dw_r/dY_i
+                const int4 *rl = N.rea + i * N.rea_len;
                 double v = 0.0;
-                for (int e = 0; e < N.rea_len; ++e) {
-                    int en = rl[e];
-                    if (en < 0) break;
-                    int r = en & 0xffff;
-                    int fl = en >> 16;
-                    double d = ((fl & 1) ? rx[nr + r] : 0.0) + ((fl & 2) ? rx[2 * nr + r] : 0.0);
-                    v = fma(N.par[r].w, d, v);
+                auto tent = [&](int4 en) {
+                    const int r = en.x & 0xffff, fl = en.x >> 16;
+                    const double q = __longlong_as_double(((long long)en.w << 32) | (unsigned)en.z);
+                    const double d = ((fl & 1) ? rx[nr + r] : 0.0) + ((fl & 2) ? rx[2 * nr + r] : 0.0);
+                    v = fma(q, d, v);
+                };
+                for (int e = 0; e < N.rea_len; e += 2) {
+                    const int4 e0 = rl[e], e1 = rl[e + 1];
+                    if (e0.x < 0) break;
+                    tent(e0);
+                    if (e1.x < 0) break;
+                    tent(e1);
                 }
                 jb[N.ns * JS + i] = v;
             }
@@ -566,24 +598,52 @@ __device__ __forceinline__ void lu_factor(const Ctx &c, Zone<NVP, L, LT> &z)
     sfor<0, NVP>([&](auto K) {
         constexpr int k = K;
         if (k >= nv) return;
-        double bv = -1.0;
+        // the search runs in the factor's precision (FP32 values compare the same
+        // way as their FP64 widenings, so the pivot is the same)
+        LT bv = LT(-1);
         int bi = 1 << 20;
         sfor<0, RPL>([&](auto S) {
             int i = row_of<NVP, L>(c, S);
-            double a = fabs((double)z.M[S][k]);
+            LT a = fabs(z.M[S][k]);
             if (z.pstep[S] > k && i < nv && a > bv) {
                 bv = a;
                 bi = i;
             }
         });
-        double gm = greduce<L>(bv, OpMax());
+        LT gm = greduce<L>(bv, OpMax());
         int p;
         if constexpr (L == 64 && RPL == 1) {
             // one row per lane: the lowest flagged lane is the lowest row
             unsigned long long m = __ballot(bv == gm && bi < (1 << 20));
             p = m ? (int)__builtin_ctzll(m) : (1 << 20);
+        } else if constexpr (RPL == 1 && L >= 2) {
+            // the same within the group's L bits of the wave-wide mask
+            const unsigned long long m = __ballot(bv == gm && bi < (1 << 20));
+            const unsigned gm_bits =
+                (unsigned)(m >> (threadIdx.x & (64 - L))) & (unsigned)((1ull << L) - 1ull);
+            p = gm_bits ? (int)__builtin_ctz(gm_bits) : (1 << 20);
         } else {
             p = greduce<L>(bv == gm ? bi : (1 << 20), OpMin());
+        }
+        if constexpr (L == 64 && RPL == 1) {
+            // Whole-wave zone: the pivot lane p is wave-uniform, so the pivot row is
+            // read from its registers with v_readlane (8 columns at a time) instead of
+            // going through LDS.
+            const LT rinv = LT(1) / lane_read(z.M[0][k], p);
+            if (c.gl == p) {
+                z.pstep[0] = k;
+                z.dinv[0] = rinv;
+            }
+            const bool act = z.pstep[0] > k;
+            const LT l = act ? z.M[0][k] * rinv : LT(0);
+            if (act) z.M[0][k] = l;
+            int pp = p;
+            sfor<k + 1, NVP>([&](auto J) {
+                if constexpr (J % 8 == 0) pp = after_s(pp, z.M[0][J - 1]);
+                z.M[0][J] = fma(-l, lane_read(z.M[0][J], pp), z.M[0][J]);
+            });
+            if (c.gl == k) z.pivlane = p;
+            return;
         }
         int pl = p & (L - 1);
         int ps = p / L;

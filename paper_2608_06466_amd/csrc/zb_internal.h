@@ -13,17 +13,21 @@ constexpr int RMAX = 4096;   // largest number of reactions
 // A network as the kernels read it.  Built once per network by the host.
 //  rct[r] = (a, b, c, d): reactants a, b and products c, d (-1 when absent).
 //  par[r] = (lnA, n, E, q).
-//  inv[i][e] = reaction index | (nu_ir << 16) for every reaction whose net
-//              stoichiometry in species i is non-zero; -1 pads the row.
-//  rea[j][e] = reaction index | (flags << 16) for every reaction with species j
-//              as a reactant: flag 1 = j is the first reactant, 2 = the second.
+//  inv[i][e], for every reaction r whose net stoichiometry nu_ir in species i is
+//              non-zero: .x = r | (nu_ir + 8) << 16, .y = a_r | (b_r + 1) << 8
+//              (the reactant columns the row's Jacobian entries go to, so no
+//              second lookup is needed); .x = -1 pads the row.
+//  rea[j][e], for every reaction with species j as a reactant: .x = r | flags << 16
+//              (flag 1: j is the first reactant, 2: the second), .zw = the bits of
+//              q_r; .x = -1 pads the row.
+//  Row lengths inv_len, rea_len are even (the kernels read two entries at a time).
 struct DevNet {
     int ns, nv, thermal, nr;
     int inv_len, rea_len;
     const int4 *rct;
     const double4 *par;
-    const int *inv;
-    const int *rea;
+    const int2 *inv;
+    const int4 *rea;
 };
 
 // One run of zones that share a network and tolerances.
