@@ -44,6 +44,8 @@ def lib():
         d, i, p = C.c_double, C.c_int, C.c_void_p
         _lib.orc_burn.restype = i
         _lib.orc_burn.argtypes = [p, p, C.c_int64, p, d, d, d, i, p, p, i]
+        _lib.orc_burn_src.restype = i
+        _lib.orc_burn_src.argtypes = [p, p, C.c_int64, p, p, d, d, d, i, p, p, i]
         _lib.orc_burn_zone.restype = i
         _lib.orc_burn_zone.argtypes = [p, p, p, d, d, d, i, p]
         _lib.orc_rhs.argtypes = [p, p, p, p]
@@ -94,8 +96,10 @@ def _as_net(net):
     return net if isinstance(net, Net) else Net(net)
 
 
-def burn(net, state, dt, rtol, atol, scale=None, max_steps=100000, nthreads=None):
-    """Burn a copy of state [zones][ns+1]; returns (state, status[zones], stats[zones,7])."""
+def burn(net, state, dt, rtol, atol, scale=None, max_steps=100000, nthreads=None, source=None):
+    """Burn a copy of state [zones][ns+1]; returns (state, status[zones], stats[zones,7]).
+
+    source: optional constant per-zone term [zones][ns+1] added to the right-hand side."""
     n = _as_net(net)
     st = np.array(state, dtype=np.float64, copy=True, order="C")
     zones = st.shape[0]
@@ -108,8 +112,11 @@ def burn(net, state, dt, rtol, atol, scale=None, max_steps=100000, nthreads=None
     stats = np.zeros((zones, 7), dtype=np.int32)
     if nthreads is None:
         nthreads = os.cpu_count() or 1
-    lib().orc_burn(n.ref, _dp(st), zones, _dp(sc), dt, rtol, atol, int(max_steps), _ip(status),
-                   _ip(stats), int(nthreads))
+    src = None if source is None else np.ascontiguousarray(source, dtype=np.float64)
+    if src is not None and src.shape != st.shape:
+        raise ValueError("source must be [zones][ns+1]")
+    lib().orc_burn_src(n.ref, _dp(st), zones, _dp(sc), _dp(src), dt, rtol, atol, int(max_steps),
+                       _ip(status), _ip(stats), int(nthreads))
     return st, status, stats
 
 

@@ -47,6 +47,7 @@ typedef struct {
     const orc_net *net;
     const double *scale;
     int nv;
+    const double *src;   /* constant source added to f (nv entries), or NULL */
 } sys_t;
 
 static double wrms(int nv, const double *v, const double *w)
@@ -65,9 +66,13 @@ static double local_error(int nv, int q, const double *dy, const double *w)
     return wrms(nv, dy, w) / (q + 1);
 }
 
+/* f(y) = network RHS + the zone's constant source (the simplified-SDC coupling of a
+   hydro update: the advective change per unit time held fixed over the burn). */
 static void rhs(const sys_t *S, const double *y, double *f, orc_stats *st)
 {
     orc_rhs(S->net, S->scale, y, f);
+    if (S->src)
+        for (int i = 0; i < S->nv; i++) f[i] += S->src[i];
     st->nfe++;
 }
 
@@ -191,7 +196,13 @@ static void correct(int nv, int q, double *Z, const double *y, const double *dy)
 int orc_burn_zone(const orc_net *net, double *row, const double *scale, double dt, double rtol,
                   double atol, int max_steps, orc_stats *st)
 {
-    sys_t S = {net, scale, orc_nvar(net)};
+    return orc_burn_zone_src(net, row, scale, NULL, dt, rtol, atol, max_steps, st);
+}
+
+int orc_burn_zone_src(const orc_net *net, double *row, const double *scale, const double *src,
+                      double dt, double rtol, double atol, int max_steps, orc_stats *st)
+{
+    sys_t S = {net, scale, orc_nvar(net), src};
     int nv = S.nv;
     double Z[(ORC_QMAX + 2) * ORC_NVMAX], Zs[(ORC_QMAX + 2) * ORC_NVMAX];
     double w[ORC_NVMAX], f0[ORC_NVMAX], f1[ORC_NVMAX], y1[ORC_NVMAX];
@@ -316,7 +327,7 @@ int orc_burn_zone(const orc_net *net, double *row, const double *scale, double d
 int orc_fixed_steps(const orc_net *net, const double *scale, int q, double h, int nsteps,
                     double *Zio, double *ys, double *errs)
 {
-    sys_t S = {net, scale, orc_nvar(net)};
+    sys_t S = {net, scale, orc_nvar(net), NULL};
     int nv = S.nv;
     orc_stats st;
     double Z[(ORC_QMAX + 2) * ORC_NVMAX], w[ORC_NVMAX], y[ORC_NVMAX], dy[ORC_NVMAX];
@@ -337,14 +348,22 @@ int orc_fixed_steps(const orc_net *net, const double *scale, int q, double h, in
 int orc_burn(const orc_net *net, double *state, int64_t zones, const double *scale, double dt,
              double rtol, double atol, int max_steps, int32_t *status, int32_t *stats, int nthreads)
 {
+    return orc_burn_src(net, state, zones, scale, NULL, dt, rtol, atol, max_steps, status, stats,
+                        nthreads);
+}
+
+int orc_burn_src(const orc_net *net, double *state, int64_t zones, const double *scale,
+                 const double *source, double dt, double rtol, double atol, int max_steps,
+                 int32_t *status, int32_t *stats, int nthreads)
+{
     if (orc_check_net(net)) return -1;
     int row = net->ns + 1;
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1) reduction(+ : bad)
     for (int64_t z = 0; z < zones; z++) {
         orc_stats st;
-        int s = orc_burn_zone(net, state + z * row, scale ? scale + z * net->nr : NULL, dt, rtol,
-                              atol, max_steps, &st);
+        int s = orc_burn_zone_src(net, state + z * row, scale ? scale + z * net->nr : NULL,
+                                  source ? source + z * row : NULL, dt, rtol, atol, max_steps, &st);
         if (status) status[z] = s;
         if (stats) memcpy(stats + z * 7, &st, sizeof(st));
         bad += (s != ORC_OK);

@@ -63,6 +63,16 @@ int orc_burn_zone(const orc_net *net, double *row, const double *scale, double d
 int orc_burn(const orc_net *net, double *state, int64_t zones, const double *scale, double dt,
              double rtol, double atol, int max_steps, int32_t *status, int32_t *stats, int nthreads);
 
+/* The same with a constant source per zone added to the right-hand side (the simplified
+   spectral-deferred-correction coupling the paper names: the hydro's advective change per
+   unit time enters the burn as a fixed term).  source is [zones][ns+1] (the T entry is used
+   only by thermal networks) or NULL. */
+int orc_burn_zone_src(const orc_net *net, double *row, const double *scale, const double *src,
+                      double dt, double rtol, double atol, int max_steps, orc_stats *st);
+int orc_burn_src(const orc_net *net, double *state, int64_t zones, const double *scale,
+                 const double *source, double dt, double rtol, double atol, int max_steps,
+                 int32_t *status, int32_t *stats, int nthreads);
+
 /* Fixed step, fixed order: nsteps BDF-q steps of size h from the Nordsieck array Z[q+1][nv];
    ys[n] = y after step n, errs[n] = its local error estimate (weights atol 1e-12, rtol 1e-8). */
 int orc_fixed_steps(const orc_net *net, const double *scale, int q, double h, int nsteps,

@@ -412,6 +412,63 @@ def test_energy_invariant():
     assert np.abs(out[:, -1] - st[:, -1]).max() > 1e-6   # T really moved
 
 
+# ------------------------------------------- constant source (SDC-style coupling)
+
+@pytest.mark.parametrize("seed", range(4))
+def test_source_on_linear_network_matches_augmented_exponential(seed):
+    """y' = K y + a with constant a: [y; 1]' = [[K, a], [0, 0]] [y; 1], so y(t) is one
+    matrix exponential of the augmented matrix (Van Loan's construction)."""
+    ns = 4 + seed % 3
+    net = W.linear_network(ns, seed)
+    K = linear_K(net)
+    rng = np.random.default_rng(100 + seed)
+    y0 = rng.dirichlet(np.ones(ns))
+    a = rng.uniform(-0.02, 0.05, ns)
+    A = np.zeros((ns + 1, ns + 1))
+    A[:ns, :ns] = K
+    A[:ns, ns] = a
+    ref = (sla.expm(A * 10.0) @ np.append(y0, 1.0))[:ns]
+    st = np.zeros((1, ns + 1))
+    st[0, :ns] = y0
+    src = np.zeros((1, ns + 1))
+    src[0, :ns] = a
+    out, status, _ = oracle.burn(net, st, 10.0, RTOL, ATOL, source=src)
+    assert status[0] == 0
+    assert gated_err(out[0, :ns], ref) < 1e-6
+    # the source really acts: without it the answer differs by far more than the tolerance
+    plain, _, _ = oracle.burn(net, st, 10.0, RTOL, ATOL)
+    assert gated_err(plain[0, :ns], ref) > 1e-3
+
+
+def test_source_alone_is_integrated_exactly():
+    """No reactions: y(t) = y0 + a t, a polynomial every BDF order reproduces exactly."""
+    net = W.linear_network(3, 0)
+    for k in ("reactant", "product"):
+        net[k] = net[k][:0]
+    for k in ("lnA", "n_exp", "E", "q"):
+        net[k] = net[k][:0]
+    y0 = np.array([[0.3, 0.5, 0.2, 0.0]])
+    a = np.array([[0.01, -0.02, 0.004, 0.0]])
+    out, status, stats = oracle.burn(net, y0, 7.0, RTOL, ATOL, source=a)
+    assert status[0] == 0
+    assert np.allclose(out[0, :3], y0[0, :3] + 7.0 * a[0, :3], rtol=1e-13, atol=1e-15)
+    assert out[0, 3] == 0.0   # the inert T slot of a network without heating
+
+
+def test_source_moves_the_species_sum_by_its_own_sum():
+    """Every reaction of the benchmark network conserves the species count, so with a source
+    the sum changes by exactly dt * sum(a) (a linear invariant, kept by BDF + exact Newton)."""
+    c2 = W.config2(16)
+    rng = np.random.default_rng(5)
+    src = np.zeros_like(c2["state"])
+    src[:, :13] = rng.uniform(-1e-3, 1e-3, (16, 13))
+    src[:, 13] = rng.uniform(-5.0, 5.0, 16)      # heating source on T
+    out, status, _ = oracle.burn(c2["net"], c2["state"], c2["dt"], RTOL, ATOL, source=src)
+    assert np.all(status == 0)
+    drift = out[:, :13].sum(1) - c2["state"][:, :13].sum(1) - c2["dt"] * src[:, :13].sum(1)
+    assert np.abs(drift).max() < 1e-12
+
+
 # ------------------------------------------------------ brute force: Radau IIA
 
 def test_radau_is_third_order():
