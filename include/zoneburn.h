@@ -130,6 +130,11 @@ typedef struct {
     const double *rate_scale;   /* DEVICE or NULL */
     int32_t *zone_status;       /* DEVICE or NULL */
     zb_zone_stats *stats;       /* DEVICE or NULL */
+    const double *source;       /* DEVICE [zones][n_species+1] or NULL: a constant term added to
+                                   each zone's right-hand side over the whole burn (the paper's
+                                   spectral-deferred-correction coupling, Software design: the
+                                   hydro's advective change per unit time enters the burn as a
+                                   fixed source).  The T entry is used only with heating. */
 } zb_segment;
 zb_err zb_burn_batch(zb_context *ctx, const zb_segment *segs, int32_t n_seg, const zb_opts *opts,
                      void *stream);

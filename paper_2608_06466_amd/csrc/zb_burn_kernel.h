@@ -381,6 +381,7 @@ struct Zone {
     double dyp[RPL];            // dy of the previous accepted step
     double iw[RPL];             // 1 / (atol + rtol |y|)
     double y[RPL], dy[RPL], f[RPL];
+    double src[RPL];            // constant source of the zone (0 without one)
     LT M[RPL][NVP];             // iteration matrix rows, then their LU factors
     LT dinv[RPL];               // 1 / pivot of the row (valid once it is a pivot row)
     LT rs[RPL];                 // row scaling of the FP32 LU
@@ -400,6 +401,7 @@ struct Ctx {
     DevNet net;
     double *state;
     const double *scale;
+    const double *source;
     int32_t *status, *stats;
     double rtol, atol, dt;
     int64_t zone;
@@ -549,7 +551,7 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
             fi = fT;
             if (WANTJ) jb[N.ns * JS + N.ns] = JTT;
         }
-        fo[s] = fi;
+        fo[s] = fi + z.src[s];
     }
 
     if (WANTJ) {
@@ -848,7 +850,8 @@ __device__ __forceinline__ int zone_start(const Ctx &c, Zone<NVP, L, LT> &z)
     for (int s = 0; s < RPL; ++s) {
         int i = row_of<NVP, L>(c, s);
         double v = (i < N.nv) ? row[i] : 0.0;
-        if (!isfinite(v)) bad = true;
+        z.src[s] = (c.source && i < N.nv) ? c.source[c.zone * (N.ns + 1) + i] : 0.0;
+        if (!isfinite(v) || !isfinite(z.src[s])) bad = true;
 #pragma unroll
         for (int j = 0; j <= QMAX; ++j) z.Z[j][s] = 0.0;
         z.Z[0][s] = v;
@@ -1157,6 +1160,7 @@ __device__ __forceinline__ void load_segment(Ctx &c, const BurnArgs &A, int seg,
     c.net.rea = uniform(S.net.rea);
     c.state = uniform(S.state);
     c.scale = uniform(S.scale);
+    c.source = uniform(S.source);
     c.status = uniform(S.status);
     c.stats = uniform(S.stats);
     c.rtol = uniform(S.rtol);

@@ -254,6 +254,7 @@ zb_err zbh::check_segment(zb_context *ctx, const zb_segment &s)
     if (s.zones > 0) {
         if (!valid_ptr(s.state, ctx->device)) return fail(ZB_EINVAL, "state is not device memory of device %d", ctx->device);
         if (!valid_ptr(s.rate_scale, ctx->device)) return fail(ZB_EINVAL, "rate_scale is not device memory");
+        if (!valid_ptr(s.source, ctx->device)) return fail(ZB_EINVAL, "source is not device memory");
         if (!valid_ptr(s.zone_status, ctx->device)) return fail(ZB_EINVAL, "zone_status is not device memory");
         if (!valid_ptr(s.stats, ctx->device)) return fail(ZB_EINVAL, "stats is not device memory");
     }
@@ -292,6 +293,7 @@ static zb_err launch_segments(zb_context *ctx, const KernelInfo *k, const zb_seg
         S.net = segs[i].net->dn;
         S.state = segs[i].state;
         S.scale = segs[i].rate_scale;
+        S.source = segs[i].source;
         S.status = segs[i].zone_status;
         S.stats = (int32_t *)segs[i].stats;
         S.zones = segs[i].zones;
@@ -467,6 +469,7 @@ extern "C" zb_err zb_burn(zb_context *ctx, const zb_network *net, double *state,
     s.rate_scale = rate_scale;
     s.zone_status = zone_status;
     s.stats = stats;
+    s.source = nullptr;
     return burn_impl(ctx, &s, 1, opts, stream);
 }
 

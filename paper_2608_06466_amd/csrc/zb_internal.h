@@ -35,6 +35,7 @@ struct Segment {
     DevNet net;
     double *state;          // [zones][ns+1]
     const double *scale;    // [zones][nr] or null
+    const double *source;   // [zones][ns+1] constant term added to f, or null
     int32_t *status;        // [zones] or null
     int32_t *stats;         // [zones][7] or null
     int64_t zones;

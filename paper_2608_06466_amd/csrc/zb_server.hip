@@ -292,6 +292,7 @@ static bool schedule_once(zb_server *S, std::unique_lock<std::mutex> &lk)
                 g.rate_scale = r->scale ? r->scale + (size_t)r->next * r->net->dn.nr : nullptr;
                 g.zone_status = r->status + r->next;
                 g.stats = r->stats + r->next;
+                g.source = nullptr;
                 segs.push_back(g);
                 L.parts.push_back({r, n});
                 r->next += n;

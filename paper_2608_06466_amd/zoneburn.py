@@ -43,7 +43,8 @@ class _Opts(C.Structure):
 class _Segment(C.Structure):
     _fields_ = [("net", C.c_void_p), ("state", C.c_void_p), ("zones", C.c_int64),
                 ("dt", C.c_double), ("rtol", C.c_double), ("atol", C.c_double),
-                ("rate_scale", C.c_void_p), ("zone_status", C.c_void_p), ("stats", C.c_void_p)]
+                ("rate_scale", C.c_void_p), ("zone_status", C.c_void_p), ("stats", C.c_void_p),
+                ("source", C.c_void_p)]
 
 
 class _ServerOpts(C.Structure):
@@ -187,10 +188,21 @@ def _check_state(net, state):
 
 
 def burn(ctx, net, state, dt, rtol, atol, rate_scale=None, precision="fp64", lanes=0,
-         max_steps=0, want_status=True, want_stats=True, stream=None):
-    """In-place burn of state [zones][ns+1]; returns (status int32[zones], stats int32[zones,7])."""
+         max_steps=0, want_status=True, want_stats=True, stream=None, source=None):
+    """In-place burn of state [zones][ns+1]; returns (status int32[zones], stats int32[zones,7]).
+
+    source: optional constant per-zone term [zones][ns+1] added to the right-hand side
+    (burned through zb_burn_batch, which takes it)."""
     import torch
     _check_state(net, state)
+    if source is not None:
+        zones = state.shape[0]
+        status = torch.empty(zones, dtype=torch.int32, device=state.device) if want_status else None
+        stats = torch.empty((zones, 7), dtype=torch.int32, device=state.device) if want_stats else None
+        burn_batch(ctx, [dict(net=net, state=state, dt=dt, rtol=rtol, atol=atol, rate_scale=rate_scale,
+                              status=status, stats=stats, source=source)],
+                   precision=precision, lanes=lanes, max_steps=max_steps, stream=stream)
+        return status, stats
     zones = state.shape[0]
     if rate_scale is not None and (rate_scale.dtype != torch.float64 or not rate_scale.is_cuda
                                    or tuple(rate_scale.shape) != (zones, net.nr)
@@ -205,6 +217,16 @@ def burn(ctx, net, state, dt, rtol, atol, rate_scale=None, precision="fp64", lan
     return status, stats
 
 
+def _src_ptr(src, state):
+    if src is None:
+        return None
+    import torch
+    if not (isinstance(src, torch.Tensor) and src.is_cuda and src.dtype == torch.float64
+            and src.shape == state.shape and src.is_contiguous()):
+        raise ValueError("source must be a contiguous float64 CUDA tensor shaped like state")
+    return src.data_ptr()
+
+
 def _segments(segments):
     arr = (_Segment * len(segments))()
     for i, s in enumerate(segments):
@@ -213,7 +235,8 @@ def _segments(segments):
                           float(s["dt"]), float(s["rtol"]), float(s["atol"]),
                           _ptr(s.get("rate_scale")).value if s.get("rate_scale") is not None else None,
                           s["status"].data_ptr() if s.get("status") is not None else None,
-                          s["stats"].data_ptr() if s.get("stats") is not None else None)
+                          s["stats"].data_ptr() if s.get("stats") is not None else None,
+                          _src_ptr(s.get("source"), s["state"]))
     return arr
 
 

@@ -305,3 +305,64 @@ def test_autotune_picks_the_fastest_qualifying_mapping(zbm):
                       lanes=best, net=net)
         assert np.array_equal(out[0], ref[0])
     net.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_constant_source_parity(zbm, precision):
+    """A constant per-zone source on the benchmark network: GPU against the oracle with the
+    same source, and the species sum moved by exactly dt * sum(a)."""
+    zb, ctx = zbm
+    c = W.config2(300)
+    rng = np.random.default_rng(5)
+    src = np.zeros_like(c["state"])
+    src[:, :13] = rng.uniform(-1e-3, 1e-3, (300, 13))
+    src[:, 13] = rng.uniform(-5.0, 5.0, 300)
+    ref = oracle.burn(c["net"], c["state"], 1.0, 1e-8, 1e-12, source=src)
+    fine = oracle.burn(c["net"], c["state"], 1.0, 1e-10, 1e-14, source=src, max_steps=10000000)
+    net = zb.Network(ctx, c["net"])
+    out = []
+    for rt, at in ((1e-8, 1e-12), (1e-10, 1e-14)):
+        st = torch.tensor(c["state"], device="cuda:0")
+        status, stats = zb.burn(ctx, net, st, 1.0, rt, at, precision=precision,
+                                source=torch.tensor(src, device="cuda:0"), max_steps=10000000)
+        zb.sync(ctx)
+        out.append((st.cpu().numpy(), status.cpu().numpy(), stats.cpu().numpy()))
+    check(f"config2 + source {precision}", out[0], (ref, fine), 1e-8, 1e-12, 14, out[1])
+    drift = out[0][0][:, :13].sum(1) - c["state"][:, :13].sum(1) - src[:, :13].sum(1)
+    assert np.abs(drift).max() < (1e-11 if precision == "fp64" else 1e-9)
+    # the source changes the answer well beyond the tolerance
+    plain = run_gpu(zb, ctx, c["net"], c["state"], 1.0, 1e-8, 1e-12, precision=precision, net=net)
+    assert np.abs(plain[0][:, :13] - out[0][0][:, :13]).max() > 1e-5
+    net.close()
+
+
+def test_constant_source_linear_network_matches_exponential(zbm):
+    """GPU burn of y' = K y + a against expm of the augmented matrix (no oracle involved)."""
+    import scipy.linalg as sla
+    zb, ctx = zbm
+    ns = 5
+    net_d = W.linear_network(ns, 3)
+    K = np.zeros((ns, ns))
+    for (a_, _), (c_, _), lk in zip(net_d["reactant"], net_d["product"], net_d["lnA"]):
+        K[a_, a_] -= np.exp(lk)
+        K[c_, a_] += np.exp(lk)
+    rng = np.random.default_rng(9)
+    zones = 40
+    y0 = rng.dirichlet(np.ones(ns), size=zones)
+    a = rng.uniform(-0.02, 0.05, (zones, ns))
+    st = np.zeros((zones, ns + 1))
+    st[:, :ns] = y0
+    src = np.zeros_like(st)
+    src[:, :ns] = a
+    t = torch.tensor(st, device="cuda:0")
+    status, _ = zb.burn(ctx, zb.Network(ctx, net_d), t, 10.0, 1e-8, 1e-12,
+                        source=torch.tensor(src, device="cuda:0"))
+    zb.sync(ctx)
+    out = t.cpu().numpy()
+    assert np.all(status.cpu().numpy() == 0)
+    for z in range(zones):
+        A = np.zeros((ns + 1, ns + 1))
+        A[:ns, :ns] = K
+        A[:ns, ns] = a[z]
+        ref = (sla.expm(A * 10.0) @ np.append(y0[z], 1.0))[:ns]
+        assert gated(out[z, :ns], ref, 1e-8, 1e-12) < 1e-6, z
