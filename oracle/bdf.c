@@ -260,11 +260,23 @@ int orc_burn_zone_src(const orc_net *net, double *row, const double *scale, cons
         }
 
         double err = local_error(nv, q, dy, w);
-        if (err > 1.0) {
+        /* Non-negativity (an inequality constraint on the abundances, as in CVODE): a step
+           that takes a species below -atol is rejected like an error-test failure and cut
+           to 0.9 of the fraction of it that keeps every species at or above -atol. */
+        double feas = 1.0;
+        for (int i = 0; i < net->ns && i < nv; i++) {
+            if (y[i] < -atol) {
+                double old = Zs[i];
+                double frac = (old + atol) / (old - y[i]);
+                feas = fmin(feas, frac);
+            }
+        }
+        if (err > 1.0 || feas < 1.0) {
             memcpy(Z, Zs, sizeof(double) * (size_t)(q + 1) * nv);
             st->netf++;
             if (++nef >= 10) { status = ORC_ERRTEST; break; }
-            double eta = fmax(0.1, 1.0 / (pow(6.0 * err, 1.0 / (q + 1)) + 1e-6));
+            double eta = err > 1.0 ? fmax(0.1, 1.0 / (pow(6.0 * err, 1.0 / (q + 1)) + 1e-6)) : 1.0;
+            if (feas < 1.0) eta = fmin(eta, fmax(0.1, 0.9 * feas));
             if (nef >= 3) eta = 0.1;
             h *= eta;
             if (nef >= 3) {
@@ -356,17 +368,40 @@ int orc_burn_src(const orc_net *net, double *state, int64_t zones, const double 
                  const double *source, double dt, double rtol, double atol, int max_steps,
                  int32_t *status, int32_t *stats, int nthreads)
 {
+    return orc_burn_retry(net, state, zones, scale, source, dt, rtol, atol, max_steps, NULL, status,
+                          stats, nthreads);
+}
+
+/* A failed zone (any status but ORC_OK) is integrated once more from its input with the
+   retry tolerances and step cap (the paper's zone-by-zone retry); success then reports
+   ORC_OK_RETRY, a second failure that run's status.  Counters add up over both runs. */
+int orc_burn_retry(const orc_net *net, double *state, int64_t zones, const double *scale,
+                   const double *source, double dt, double rtol, double atol, int max_steps,
+                   const orc_retry *retry, int32_t *status, int32_t *stats, int nthreads)
+{
     if (orc_check_net(net)) return -1;
     int row = net->ns + 1;
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1) reduction(+ : bad)
     for (int64_t z = 0; z < zones; z++) {
         orc_stats st;
-        int s = orc_burn_zone_src(net, state + z * row, scale ? scale + z * net->nr : NULL,
-                                  source ? source + z * row : NULL, dt, rtol, atol, max_steps, &st);
+        double in[ORC_NVMAX + 1];
+        double *y = state + z * row;
+        const double *sc = scale ? scale + z * net->nr : NULL;
+        const double *sr = source ? source + z * row : NULL;
+        memcpy(in, y, sizeof(double) * row);
+        int s = orc_burn_zone_src(net, y, sc, sr, dt, rtol, atol, max_steps, &st);
+        if (s != ORC_OK && retry && retry->enabled) {
+            orc_stats st2;
+            memcpy(y, in, sizeof(double) * row);
+            s = orc_burn_zone_src(net, y, sc, sr, dt, retry->rtol, retry->atol, retry->max_steps, &st2);
+            if (s == ORC_OK) s = ORC_OK_RETRY;
+            st.nst += st2.nst; st.nfe += st2.nfe; st.nje += st2.nje; st.nlu += st2.nlu;
+            st.nni += st2.nni; st.netf += st2.netf; st.ncf += st2.ncf;
+        }
         if (status) status[z] = s;
         if (stats) memcpy(stats + z * 7, &st, sizeof(st));
-        bad += (s != ORC_OK);
+        bad += (s != ORC_OK && s != ORC_OK_RETRY);
     }
     return bad;
 }

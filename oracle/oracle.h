@@ -24,7 +24,8 @@
 #define ORC_NVMAX 64
 #define ORC_QMAX 5
 
-enum { ORC_OK = 0, ORC_MAXSTEPS = 1, ORC_ERRTEST = 2, ORC_CONV = 3, ORC_HMIN = 4, ORC_NONFINITE = 5 };
+enum { ORC_OK = 0, ORC_MAXSTEPS = 1, ORC_ERRTEST = 2, ORC_CONV = 3, ORC_HMIN = 4, ORC_NONFINITE = 5,
+       ORC_OK_RETRY = 6 /* failed, then succeeded on the retry */ };
 
 typedef struct {
     int ns;            /* species */
@@ -80,5 +81,12 @@ int orc_fixed_steps(const orc_net *net, const double *scale, int q, double h, in
 
 /* Brute force: 2-stage Radau IIA on a geometric mesh (first step h0), full Newton. */
 int orc_radau(const orc_net *net, const double *scale, double *y, double dt, int64_t nsteps, double h0);
+
+/* Zone-by-zone retry of failed zones (the paper: retry an integration with different
+   tolerances).  enabled = 0 turns it off. */
+typedef struct { int enabled; double rtol, atol; int max_steps; } orc_retry;
+int orc_burn_retry(const orc_net *net, double *state, int64_t zones, const double *scale,
+                   const double *source, double dt, double rtol, double atol, int max_steps,
+                   const orc_retry *retry, int32_t *status, int32_t *stats, int nthreads);
 
 #endif

@@ -315,7 +315,7 @@ def test_constant_source_parity(zbm, precision):
     c = W.config2(300)
     rng = np.random.default_rng(5)
     src = np.zeros_like(c["state"])
-    src[:, :13] = rng.uniform(-1e-3, 1e-3, (300, 13))
+    src[:, :13] = rng.uniform(0.0, 1e-3, (300, 13))
     src[:, 13] = rng.uniform(-5.0, 5.0, 300)
     ref = oracle.burn(c["net"], c["state"], 1.0, 1e-8, 1e-12, source=src)
     fine = oracle.burn(c["net"], c["state"], 1.0, 1e-10, 1e-14, source=src, max_steps=10000000)
@@ -349,7 +349,7 @@ def test_constant_source_linear_network_matches_exponential(zbm):
     rng = np.random.default_rng(9)
     zones = 40
     y0 = rng.dirichlet(np.ones(ns), size=zones)
-    a = rng.uniform(-0.02, 0.05, (zones, ns))
+    a = rng.uniform(0.0, 0.05, (zones, ns))
     st = np.zeros((zones, ns + 1))
     st[:, :ns] = y0
     src = np.zeros_like(st)

@@ -423,7 +423,7 @@ def test_source_on_linear_network_matches_augmented_exponential(seed):
     K = linear_K(net)
     rng = np.random.default_rng(100 + seed)
     y0 = rng.dirichlet(np.ones(ns))
-    a = rng.uniform(-0.02, 0.05, ns)
+    a = rng.uniform(0.0, 0.05, ns)        # a feed: the abundances stay non-negative
     A = np.zeros((ns + 1, ns + 1))
     A[:ns, :ns] = K
     A[:ns, ns] = a
@@ -448,7 +448,7 @@ def test_source_alone_is_integrated_exactly():
     for k in ("lnA", "n_exp", "E", "q"):
         net[k] = net[k][:0]
     y0 = np.array([[0.3, 0.5, 0.2, 0.0]])
-    a = np.array([[0.01, -0.02, 0.004, 0.0]])
+    a = np.array([[0.01, -0.02, 0.004, 0.0]])   # 0.5 - 7 * 0.02 stays positive
     out, status, stats = oracle.burn(net, y0, 7.0, RTOL, ATOL, source=a)
     assert status[0] == 0
     assert np.allclose(out[0, :3], y0[0, :3] + 7.0 * a[0, :3], rtol=1e-13, atol=1e-15)
@@ -461,12 +461,61 @@ def test_source_moves_the_species_sum_by_its_own_sum():
     c2 = W.config2(16)
     rng = np.random.default_rng(5)
     src = np.zeros_like(c2["state"])
-    src[:, :13] = rng.uniform(-1e-3, 1e-3, (16, 13))
-    src[:, 13] = rng.uniform(-5.0, 5.0, 16)      # heating source on T
+    src[:, :13] = rng.uniform(0.0, 1e-3, (16, 13))
+    src[:, 13] = rng.uniform(-5.0, 5.0, 16)      # heating or cooling source on T
     out, status, _ = oracle.burn(c2["net"], c2["state"], c2["dt"], RTOL, ATOL, source=src)
     assert np.all(status == 0)
     drift = out[:, :13].sum(1) - c2["state"][:, :13].sum(1) - c2["dt"] * src[:, :13].sum(1)
     assert np.abs(drift).max() < 1e-12
+
+
+# ------------------------------------------------ non-negativity constraint
+
+def test_loose_tolerance_zones_match_scipy_radau():
+    """At rtol 1e-6 zone 43 of this input drains a species linearly through zero: every higher
+    derivative is small, so the local-error test alone accepts a step to -1.5e-3 (the true
+    value is 8.6e-15).  The abundance constraint rejects such steps; the burn then agrees with
+    an independent tight Radau solution (scipy) to the loose tolerance."""
+    c = W.config2(96)
+    idx = [43, 7]
+    out, status, _ = oracle.burn(c["net"], c["state"][idx], 1.0, 1e-6, 1e-10)
+    assert np.all(status == 0)
+    assert out[:, :13].min() >= -1e-10
+    for k, z in enumerate(idx):
+        r = solve_ivp(lambda t, y: oracle.rhs(c["net"], y), (0.0, 1.0), c["state"][z, :14],
+                      method="Radau", rtol=1e-12, atol=1e-20,
+                      jac=lambda t, y: oracle.jac(c["net"], y))
+        assert r.status == 0
+        assert gated_err(out[k, :14], r.y[:, -1], rtol=1e-6, atol=1e-10) < 1e-4, z
+
+
+# ------------------------------------------------------- zone-by-zone retry
+
+def test_retry_reruns_failed_zones_from_their_input():
+    """A step cap of 1500 fails most zones of the benchmark network; each retried zone is the
+    plain burn of its original input at the retry tolerances, its status 6, its counters the
+    sum of both runs, and zones that did not fail are untouched by the retry."""
+    c = W.config2(96)
+    plain = oracle.burn(c["net"], c["state"], 1.0, RTOL, ATOL, max_steps=1500)
+    rt = oracle.burn(c["net"], c["state"], 1.0, RTOL, ATOL, max_steps=1500,
+                     retry=(1e-6, 1e-10, 100000))
+    failed = plain[1] != 0
+    assert 10 < failed.sum() < 96
+    assert np.all(rt[1][failed] == 6) and np.all(rt[1][~failed] == 0)
+    assert np.array_equal(rt[0][~failed], plain[0][~failed])
+    again = oracle.burn(c["net"], c["state"][failed], 1.0, 1e-6, 1e-10)
+    assert np.array_equal(rt[0][failed], again[0])
+    assert np.array_equal(rt[2][failed], plain[2][failed] + again[2])
+    # the retried answers meet their own tolerance against the tight reference
+    fine = oracle.burn(c["net"], c["state"][failed], 1.0, 1e-11, 1e-15)
+    assert gated_err(rt[0][failed][:, :14], fine[0][:, :14], rtol=1e-6, atol=1e-10) < 1e-3
+
+
+def test_retry_that_fails_again_reports_the_retry_status():
+    c = W.config2(8)
+    rt = oracle.burn(c["net"], c["state"], 1.0, RTOL, ATOL, max_steps=50, retry=(RTOL, ATOL, 60))
+    assert np.all(rt[1] == 1)                   # MAXSTEPS both times
+    assert np.all(rt[2][:, 0] == 110)           # 50 + 60 accepted steps
 
 
 # ------------------------------------------------------ brute force: Radau IIA
