@@ -47,7 +47,8 @@ typedef enum {
     ZB_ZONE_ERRTEST = 2,    /* ten consecutive error-test failures */
     ZB_ZONE_CONV = 3,       /* ten consecutive Newton failures */
     ZB_ZONE_HMIN = 4,       /* step size fell below the resolution of t */
-    ZB_ZONE_NONFINITE = 5   /* non-finite initial state or right-hand side */
+    ZB_ZONE_NONFINITE = 5,  /* non-finite initial state or right-hand side */
+    ZB_ZONE_OK_RETRY = 6    /* failed, then reached dt on the zone-by-zone retry (valid result) */
 } zb_zone_status;
 
 /* Per-zone counters: accepted steps, RHS evaluations, Jacobians, LU factorizations,
@@ -82,6 +83,14 @@ typedef struct {
                             its triangular solves in FP32 (rows and columns scaled by the error
                             weights); RHS, Jacobian, residual, update, norms and control in FP64 */
     int32_t mapping;     /* ZB_MAP_AUTO or lanes per zone (1, 2, 4, 8, 16, 32, 64) */
+    int32_t retry;       /* 1: zone-by-zone retry (the paper, Software design: a failing zone is
+                            integrated again with different tolerances instead of stopping the
+                            run).  A zone that ends with any failure status is integrated once
+                            more from its input with retry_rtol, retry_atol and retry_max_steps;
+                            success reports ZB_ZONE_OK_RETRY, a second failure that run's status;
+                            its counters add up over both runs.  0: off */
+    double retry_rtol, retry_atol;   /* > 0 when retry is on */
+    int32_t retry_max_steps;         /* <= 0: the same as max_steps */
     int32_t reserved;
 } zb_opts;
 
@@ -180,7 +189,7 @@ typedef struct {
 } zb_server_opts;
 
 typedef struct {
-    int64_t zones, zones_ok;
+    int64_t zones, zones_ok;   /* zones_ok counts ZB_ZONE_OK and ZB_ZONE_OK_RETRY */
     double queue_s;          /* submit -> admission (device memory granted) */
     double first_launch_s;   /* submit -> first slice launched */
     double latency_s;        /* submit -> last slice finished on the device */

@@ -382,6 +382,8 @@ struct Zone {
     double iw[RPL];             // 1 / (atol + rtol |y|)
     double y[RPL], dy[RPL], f[RPL];
     double src[RPL];            // constant source of the zone (0 without one)
+    double rtol, atol;          // tolerances of the current run (the retry may loosen them)
+    int max_steps, tries;
     LT M[RPL][NVP];             // iteration matrix rows, then their LU factors
     LT dinv[RPL];               // 1 / pivot of the row (valid once it is a pivot row)
     LT rs[RPL];                 // row scaling of the FP32 LU
@@ -799,7 +801,7 @@ __device__ __forceinline__ void set_weights(const Ctx &c, Zone<NVP, L, LT> &z)
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
         int i = row_of<NVP, L>(c, s);
-        double w = c.atol + c.rtol * fabs(z.Z[0][s]);
+        double w = z.atol + z.rtol * fabs(z.Z[0][s]);
         z.iw[s] = (i < c.net.nv) ? 1.0 / w : 0.0;
         if (i < NVP) wb[i] = (i < c.net.nv) ? w : 1.0;
     }
@@ -895,11 +897,11 @@ __device__ __forceinline__ int zone_start(const Ctx &c, Zone<NVP, L, LT> &z)
 
 // One step attempt.  Returns RUNNING, or the zone's final status.
 template <int NVP, int L, class LT>
-__device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z, int max_steps)
+__device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
 {
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
     const double tau = 0.03;
-    if (z.nst >= max_steps) return ZB_ZONE_MAXSTEPS;
+    if (z.nst >= z.max_steps) return ZB_ZONE_MAXSTEPS;
     bool last = false;
     if (z.t + z.h >= c.dt * (1.0 - 4.0 * DBL_EPSILON)) {
         double eta = (c.dt - z.t) / z.h;
@@ -975,11 +977,27 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z, i
     }
 
     const double err = wrms(c, z, z.dy) / (double)(z.q + 1);
-    if (err > 1.0) {
+    // Non-negativity of the abundances: a step that takes a species below -atol fails
+    // like an error test and is cut to 0.9 of its feasible fraction (from the saved Z_0).
+    double feas = 1.0;
+    {
+        const double *zs = c.S + c.lay.zs;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) {
+            const int i = row_of<NVP, L>(c, s);
+            if (i < c.net.ns && z.y[s] < -z.atol) {
+                const double old = zs[s * L + c.gl];   // Z_0 before the prediction
+                feas = fmin(feas, (old + z.atol) / (old - z.y[s]));
+            }
+        }
+        feas = greduce<L>(feas, OpMin());
+    }
+    if (err > 1.0 || feas < 1.0) {
         restore_history(c, z);
         z.netf++;
         if (++z.nefc >= 10) return ZB_ZONE_ERRTEST;
-        double eta = fmax(0.1, 1.0 / (pow(6.0 * err, 1.0 / (double)(z.q + 1)) + 1e-6));
+        double eta = err > 1.0 ? fmax(0.1, 1.0 / (pow(6.0 * err, 1.0 / (double)(z.q + 1)) + 1e-6)) : 1.0;
+        if (feas < 1.0) eta = fmin(eta, fmax(0.1, 0.9 * feas));
         if (z.nefc >= 3) eta = 0.1;
         z.h *= eta;
         if (z.nefc >= 3) {
@@ -1115,10 +1133,15 @@ __device__ __forceinline__ void zone_finish(const Ctx &c, Zone<NVP, L, LT> &z, i
         if (c.status) c.status[c.zone] = status;
         if (c.stats) {
             int32_t *o = c.stats + c.zone * 7;
-            o[0] = z.nst; o[1] = z.nfe; o[2] = z.nje; o[3] = z.nlu;
-            o[4] = z.nni; o[5] = z.netf; o[6] = z.ncf;
+            int add[7] = {0, 0, 0, 0, 0, 0, 0};
+            if (z.tries > 0) {
+                const int *cnt = (const int *)(c.S + c.lay.cnt);
+                for (int k = 0; k < 7; ++k) add[k] = cnt[k];
+            }
+            o[0] = z.nst + add[0]; o[1] = z.nfe + add[1]; o[2] = z.nje + add[2]; o[3] = z.nlu + add[3];
+            o[4] = z.nni + add[4]; o[5] = z.netf + add[5]; o[6] = z.ncf + add[6];
         }
-        if (status != ZB_ZONE_OK) atomicAdd(A.nfail, 1ull);
+        if (status != ZB_ZONE_OK && status != ZB_ZONE_OK_RETRY) atomicAdd(A.nfail, 1ull);
     }
 }
 
@@ -1206,6 +1229,10 @@ void burn_kernel(BurnArgs A)
                 dry = true;
             } else {
                 c.zone = (int64_t)item;
+                z.rtol = c.rtol;
+                z.atol = c.atol;
+                z.max_steps = A.max_steps;
+                z.tries = 0;
                 int st = zone_start(c, z);
                 if (st == RUNNING)
                     need = false;
@@ -1226,8 +1253,26 @@ void burn_kernel(BurnArgs A)
             continue;
         }
         if (!need) {
-            int st = zone_attempt(c, z, A.max_steps);
+            int st = zone_attempt(c, z);
             if (st != RUNNING) {
+                if (st != ZB_ZONE_OK && A.retry && z.tries == 0) {
+                    // Zone-by-zone retry with the retry tolerances, from the zone's input
+                    // (still in memory: results are written only when a zone ends).  The
+                    // first run's counters wait in LDS and are added at the end.
+                    if (c.gl == 0) {
+                        int *cnt = (int *)(c.S + c.lay.cnt);
+                        cnt[0] = z.nst; cnt[1] = z.nfe; cnt[2] = z.nje; cnt[3] = z.nlu;
+                        cnt[4] = z.nni; cnt[5] = z.netf; cnt[6] = z.ncf;
+                    }
+                    z.rtol = A.retry_rtol;
+                    z.atol = A.retry_atol;
+                    z.max_steps = A.retry_max_steps;
+                    z.tries = 1;
+                    st = zone_start(c, z);
+                    if (st == RUNNING) continue;
+                } else if (st == ZB_ZONE_OK && z.tries > 0) {
+                    st = ZB_ZONE_OK_RETRY;
+                }
                 zone_finish(c, z, st, A);
                 need = true;
             }

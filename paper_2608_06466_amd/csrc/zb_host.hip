@@ -280,8 +280,28 @@ int zbh::blocks_per_cu(const KernelInfo *k, int max_nr)
 
 // One persistent launch over segments that all use the same kernel.  queue:
 // MAXSEG device counters the launch clears first; nfail: failed-zone counter.
+namespace {
+struct RunOpts {
+    int max_steps, retry, retry_max_steps;
+    double retry_rtol, retry_atol;
+};
+}  // namespace
+
+static RunOpts run_opts(const zb_opts *o)
+{
+    RunOpts r{100000, 0, 100000, 0.0, 0.0};
+    if (o && o->max_steps > 0) r.max_steps = o->max_steps;
+    if (o && o->retry) {
+        r.retry = 1;
+        r.retry_rtol = o->retry_rtol;
+        r.retry_atol = o->retry_atol;
+        r.retry_max_steps = o->retry_max_steps > 0 ? o->retry_max_steps : r.max_steps;
+    }
+    return r;
+}
+
 static zb_err launch_segments(zb_context *ctx, const KernelInfo *k, const zb_segment *segs, int n,
-                              int max_steps, hipStream_t stream, unsigned long long *queue,
+                              const RunOpts &ro, hipStream_t stream, unsigned long long *queue,
                               unsigned long long *nfail, float *ms_out)
 {
     BurnArgs A;
@@ -306,7 +326,11 @@ static zb_err launch_segments(zb_context *ctx, const KernelInfo *k, const zb_seg
     if (total == 0) return ZB_OK;
     A.nseg = n;
     A.max_nr = max_nr;
-    A.max_steps = max_steps;
+    A.max_steps = ro.max_steps;
+    A.retry = ro.retry;
+    A.retry_max_steps = ro.retry_max_steps;
+    A.retry_rtol = ro.retry_rtol;
+    A.retry_atol = ro.retry_atol;
     A.queue = queue;
     A.nfail = nfail;
 
@@ -355,6 +379,10 @@ static zb_err plan_groups(zb_context *ctx, const zb_segment *segs, int n, const 
     if (opts && opts->mapping != ZB_MAP_AUTO &&
         (opts->mapping < 1 || opts->mapping > 64 || (opts->mapping & (opts->mapping - 1))))
         return fail(ZB_EINVAL, "mapping must be 0 or a power of two 1..64");
+    if (opts && opts->retry &&
+        !(isfinite(opts->retry_rtol) && opts->retry_rtol > 0.0 && isfinite(opts->retry_atol) &&
+          opts->retry_atol > 0.0))
+        return fail(ZB_EINVAL, "retry needs finite retry_rtol > 0 and retry_atol > 0");
     for (int i = 0; i < n; ++i) {
         zb_err e = check_segment(ctx, segs[i]);
         if (e != ZB_OK) return e;
@@ -413,7 +441,7 @@ zb_err zbh::burn_impl(zb_context *ctx, const zb_segment *segs, int n, const zb_o
     zb_err e = plan_groups(ctx, segs, n, opts, force_lanes, groups);
     if (e != ZB_OK) return e;
     if (groups.empty()) return ZB_OK;
-    const int max_steps = (opts && opts->max_steps > 0) ? opts->max_steps : 100000;
+    const RunOpts ro = run_opts(opts);
     const int ng = (int)groups.size();
     if (ws && ng > ws->launches)
         return fail(ZB_EINVAL, "workspace holds queues for %d launches, %d needed", ws->launches, ng);
@@ -432,7 +460,7 @@ zb_err zbh::burn_impl(zb_context *ctx, const zb_segment *segs, int n, const zb_o
     hipStream_t s0 = (hipStream_t)stream;
     if (ng == 1)
         return launch_segments(ctx, groups[0].k, groups[0].segs.data(), (int)groups[0].segs.size(),
-                               max_steps, s0, queue[0], nfail, ms_out);
+                               ro, s0, queue[0], nfail, ms_out);
     // Several kernel classes: the costliest runs on the caller's stream and the
     // others on side streams forked from it and joined back, so the classes share
     // the GPU (a class's tail is filled by the others) instead of running in turn.
@@ -445,7 +473,7 @@ zb_err zbh::burn_impl(zb_context *ctx, const zb_segment *segs, int n, const zb_o
     for (int i = 0; i < ng; ++i) {
         hipStream_t s = i == 0 ? s0 : ctx->side[(i - 1) % nside];
         e = launch_segments(ctx, groups[i].k, groups[i].segs.data(), (int)groups[i].segs.size(),
-                            max_steps, s, queue[i], nfail, nullptr);
+                            ro, s, queue[i], nfail, nullptr);
         if (e != ZB_OK) return e;
     }
     for (int j = 0; j < nside; ++j) {
@@ -591,7 +619,8 @@ extern "C" zb_err zb_autotune(zb_context *ctx, const zb_network *net, const doub
     int best = 0;
     float best_ms = 0.f;
     bool have_ref = false;
-    zb_opts o = {0, precision, 0, 0};
+    zb_opts o{};
+    o.precision = precision;
     zb_err res = ZB_OK;
     for (int li = 0, lanes = 1; lanes <= 64; ++li, lanes *= 2) {
         if (times_ms) times_ms[li] = -1.f;

@@ -49,13 +49,15 @@ struct BurnArgs {
     int nseg;
     int max_nr;                    // largest reaction count of the segments (sizes the LDS)
     int max_steps;
+    int retry, retry_max_steps;    // zone-by-zone retry of failed zones (0: off)
+    double retry_rtol, retry_atol;
     unsigned long long *queue;     // [nseg] next zone of each segment (zeroed before the launch)
     unsigned long long *nfail;     // zones that ended with a non-OK status
 };
 
 // Per-group LDS layout (in doubles).  Everything a zone group exchanges lives here.
 struct LdsLayout {
-    int xch, zs, ybuf, wbuf, prow, ks, rx, jbuf, total;
+    int xch, cnt, zs, ybuf, wbuf, prow, ks, rx, jbuf, total;
 };
 
 // nvl = lanes per zone x rows per lane (>= nvp): one slot per lane and local row.
@@ -64,6 +66,7 @@ __host__ __device__ inline LdsLayout lds_layout(int nvp, int nvl, int nr)
     LdsLayout o;
     int p = 0;
     o.xch = p;  p += 2;
+    o.cnt = p;  p += 4;               // counters of a zone's first run while it is retried
     o.zs = p;   p += (QMAX + 1) * nvl;
     o.ybuf = p; p += nvp;
     o.wbuf = p; p += nvp;

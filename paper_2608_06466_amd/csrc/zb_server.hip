@@ -384,6 +384,9 @@ extern "C" zb_err zb_server_create(zb_context *ctx, const zb_server_opts *so, zb
     if (bo.precision != ZB_FP64 && bo.precision != ZB_MIXED) return fail(ZB_EINVAL, "precision %d", bo.precision);
     if (bo.mapping != ZB_MAP_AUTO && (bo.mapping < 1 || bo.mapping > 64 || (bo.mapping & (bo.mapping - 1))))
         return fail(ZB_EINVAL, "mapping must be 0 or a power of two 1..64");
+    if (bo.retry && !(isfinite(bo.retry_rtol) && bo.retry_rtol > 0.0 && isfinite(bo.retry_atol) &&
+                      bo.retry_atol > 0.0))
+        return fail(ZB_EINVAL, "retry needs finite retry_rtol > 0 and retry_atol > 0");
     DeviceGuard g(ctx->device);
     zb_server *S = new (std::nothrow) zb_server();
     if (!S) return fail(ZB_ENOMEM, "host allocation failed");
@@ -545,7 +548,7 @@ extern "C" zb_err zb_server_fetch(zb_server *S, uint64_t ticket, double *host_st
         info->zones = z;
         int64_t ok = 0;
         if (e == ZB_OK)
-            for (int64_t i = 0; i < z; ++i) ok += st_dst[i] == ZB_ZONE_OK;
+            for (int64_t i = 0; i < z; ++i) ok += st_dst[i] == ZB_ZONE_OK || st_dst[i] == ZB_ZONE_OK_RETRY;
         info->zones_ok = ok;
         info->queue_s = r->t_admit - r->t_submit;
         info->latency_s = r->t_done - r->t_submit;
