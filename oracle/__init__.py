@@ -48,6 +48,8 @@ def lib():
         _lib.orc_burn_src.argtypes = [p, p, C.c_int64, p, p, d, d, d, i, p, p, i]
         _lib.orc_burn_retry.restype = i
         _lib.orc_burn_retry.argtypes = [p, p, C.c_int64, p, p, d, d, d, i, p, p, p, i]
+        _lib.orc_burn_ex.restype = i
+        _lib.orc_burn_ex.argtypes = [p, p, C.c_int64, p, p, d, d, d, i, i, p, p, p, i]
         _lib.orc_burn_zone.restype = i
         _lib.orc_burn_zone.argtypes = [p, p, p, d, d, d, i, p]
         _lib.orc_rhs.argtypes = [p, p, p, p]
@@ -104,12 +106,13 @@ class _Retry(C.Structure):
 
 
 def burn(net, state, dt, rtol, atol, scale=None, max_steps=100000, nthreads=None, source=None,
-         retry=None):
+         retry=None, jac_policy=0):
     """Burn a copy of state [zones][ns+1]; returns (state, status[zones], stats[zones,7]).
 
     source: optional constant per-zone term [zones][ns+1] added to the right-hand side.
     retry: optional (rtol, atol, max_steps) for a second run of every failed zone from its
-    input; such a zone then reports status 6 when the retry succeeds."""
+    input; such a zone then reports status 6 when the retry succeeds.
+    jac_policy: 0 Jacobian and LU every step attempt, 1 VODE-style reuse."""
     n = _as_net(net)
     st = np.array(state, dtype=np.float64, copy=True, order="C")
     zones = st.shape[0]
@@ -126,8 +129,9 @@ def burn(net, state, dt, rtol, atol, scale=None, max_steps=100000, nthreads=None
     if src is not None and src.shape != st.shape:
         raise ValueError("source must be [zones][ns+1]")
     rt = None if retry is None else _Retry(1, float(retry[0]), float(retry[1]), int(retry[2]))
-    lib().orc_burn_retry(n.ref, _dp(st), zones, _dp(sc), _dp(src), dt, rtol, atol, int(max_steps),
-                         None if rt is None else C.byref(rt), _ip(status), _ip(stats), int(nthreads))
+    lib().orc_burn_ex(n.ref, _dp(st), zones, _dp(sc), _dp(src), dt, rtol, atol, int(max_steps),
+                      int(jac_policy), None if rt is None else C.byref(rt), _ip(status), _ip(stats),
+                      int(nthreads))
     return st, status, stats
 
 

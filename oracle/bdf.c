@@ -138,33 +138,64 @@ static void predict(int nv, int q, double *Z)
             for (int i = 0; i < nv; i++) Z[(size_t)(j - 1) * nv + i] += Z[(size_t)j * nv + i];
 }
 
-/* One Newton solve of the corrector.  On success dy holds y - y_pred and y the new value.
-   Returns 0 on convergence, 1 on failure. */
-static int newton(const sys_t *S, int q, double h, const double *Z, const double *w, double rtol,
-                  double *y, double *dy, orc_stats *st)
+/* Iteration-matrix state of a zone.  Policy 0 (the default) evaluates J and factors
+   M = I - gamma J on every step attempt.  Policy 1 is the VODE-style reuse of the
+   Brown-Byrne-Hindmarsh paper: M is kept across steps and re-formed only when gamma has
+   changed by more than 30 % since it was formed, after 20 steps, or after a Newton
+   failure with a Jacobian from an earlier step; a re-formed M evaluates a fresh J unless
+   the saved one is younger than 50 steps and gamma moved by less than 20 % (an age-only
+   refresh).  With M formed at gamma_M != gamma the Newton correction is scaled by
+   2 / (1 + gamma / gamma_M), the factor VODE applies to a lagged matrix. */
+typedef struct {
+    int policy;
+    int have_j, have_m;
+    int nst_j, nst_m;            /* nst when J was evaluated / M was factored */
+    double gamma_m;
+    int sing;
+    double J[ORC_NVMAX * ORC_NVMAX], LU[ORC_NVMAX * ORC_NVMAX];
+    int piv[ORC_NVMAX];
+} jac_t;
+
+static void form_lu(const sys_t *S, jac_t *J, double gamma, orc_stats *st)
 {
     int nv = S->nv;
-    double l[ORC_QMAX + 1], M[ORC_NVMAX * ORC_NVMAX], f[ORC_NVMAX], b[ORC_NVMAX];
-    int piv[ORC_NVMAX];
-    orc_lcoef(q, l);
-    double gamma = h * l[0];
-
-    orc_jac(S->net, S->scale, Z, M);
-    st->nje++;
     for (int i = 0; i < nv; i++)
-        for (int j = 0; j < nv; j++) M[i * nv + j] = (i == j ? 1.0 : 0.0) - gamma * M[i * nv + j];
-    int sing = orc_lu(nv, M, piv);
+        for (int j = 0; j < nv; j++) J->LU[i * nv + j] = (i == j ? 1.0 : 0.0) - gamma * J->J[i * nv + j];
+    J->sing = orc_lu(nv, J->LU, J->piv);
     st->nlu++;
+    J->gamma_m = gamma;
+    J->have_m = 1;
+    J->nst_m = st->nst;
+}
 
+static void eval_jac(const sys_t *S, jac_t *J, const double *y, orc_stats *st)
+{
+    orc_jac(S->net, S->scale, y, J->J);
+    st->nje++;
+    J->have_j = 1;
+    J->nst_j = st->nst;
+}
+
+/* The Newton iterations with the current M.  Returns 0 on convergence, 1 on failure. */
+static int newton_iter(const sys_t *S, const jac_t *J, int q, double h, const double *Z,
+                       const double *w, double *y, double *dy, orc_stats *st)
+{
+    int nv = S->nv;
+    double l[ORC_QMAX + 1], f[ORC_NVMAX], b[ORC_NVMAX];
+    orc_lcoef(q, l);
+    const double gamma = h * l[0];
+    const double rc = gamma / J->gamma_m;          /* 1 with a matrix formed at this gamma */
+    const double cscale = (rc != 1.0) ? 2.0 / (1.0 + rc) : 1.0;
     const double tau = 0.03;
-    (void)rtol;
     for (int i = 0; i < nv; i++) { y[i] = Z[i]; dy[i] = 0.0; }
     double dprev = 0.0;
     for (int m = 0; m < 4; m++) {
         rhs(S, y, f, st);
         for (int i = 0; i < nv; i++) b[i] = -(dy[i] - l[0] * (h * f[i] - Z[nv + i]));
-        if (sing) return 1;
-        orc_lu_solve(nv, M, piv, b);
+        if (J->sing) return 1;
+        orc_lu_solve(nv, J->LU, J->piv, b);
+        if (cscale != 1.0)
+            for (int i = 0; i < nv; i++) b[i] *= cscale;
         for (int i = 0; i < nv; i++) { y[i] += b[i]; dy[i] += b[i]; }
         double d = wrms(nv, b, w);
         st->nni++;
@@ -179,6 +210,36 @@ static int newton(const sys_t *S, int q, double h, const double *Z, const double
         dprev = d;
     }
     return 1;
+}
+
+/* One Newton solve of the corrector.  On success dy holds y - y_pred and y the new value.
+   Returns 0 on convergence, 1 on failure. */
+static int newton(const sys_t *S, jac_t *J, int q, double h, const double *Z, const double *w,
+                  double *y, double *dy, orc_stats *st)
+{
+    double l[ORC_QMAX + 1];
+    orc_lcoef(q, l);
+    const double gamma = h * l[0];
+    if (J->policy == 0) {
+        eval_jac(S, J, Z, st);
+        form_lu(S, J, gamma, st);
+        return newton_iter(S, J, q, h, Z, w, y, dy, st);
+    }
+    int fresh = 0;   /* J evaluated at this attempt's prediction */
+    const double drc = J->have_m ? fabs(gamma / J->gamma_m - 1.0) : 1.0;
+    if (!J->have_m || drc > 0.3 || st->nst >= J->nst_m + 20) {
+        if (!J->have_j || st->nst >= J->nst_j + 50 || drc >= 0.2) {
+            eval_jac(S, J, Z, st);
+            fresh = 1;
+        }
+        form_lu(S, J, gamma, st);
+    }
+    if (newton_iter(S, J, q, h, Z, w, y, dy, st) == 0) return 0;
+    if (fresh) return 1;
+    /* failure with a Jacobian from an earlier step: refresh it here and retry once */
+    eval_jac(S, J, Z, st);
+    form_lu(S, J, gamma, st);
+    return newton_iter(S, J, q, h, Z, w, y, dy, st);
 }
 
 /* Corrector update of the history after an accepted step. */
@@ -196,13 +257,23 @@ static void correct(int nv, int q, double *Z, const double *y, const double *dy)
 int orc_burn_zone(const orc_net *net, double *row, const double *scale, double dt, double rtol,
                   double atol, int max_steps, orc_stats *st)
 {
-    return orc_burn_zone_src(net, row, scale, NULL, dt, rtol, atol, max_steps, st);
+    return orc_burn_zone_ex(net, row, scale, NULL, dt, rtol, atol, max_steps, 0, st);
 }
 
 int orc_burn_zone_src(const orc_net *net, double *row, const double *scale, const double *src,
                       double dt, double rtol, double atol, int max_steps, orc_stats *st)
 {
+    return orc_burn_zone_ex(net, row, scale, src, dt, rtol, atol, max_steps, 0, st);
+}
+
+int orc_burn_zone_ex(const orc_net *net, double *row, const double *scale, const double *src,
+                     double dt, double rtol, double atol, int max_steps, int jac_policy,
+                     orc_stats *st)
+{
     sys_t S = {net, scale, orc_nvar(net), src};
+    jac_t J;
+    memset(&J, 0, sizeof J);
+    J.policy = jac_policy;
     int nv = S.nv;
     double Z[(ORC_QMAX + 2) * ORC_NVMAX], Zs[(ORC_QMAX + 2) * ORC_NVMAX];
     double w[ORC_NVMAX], f0[ORC_NVMAX], f1[ORC_NVMAX], y1[ORC_NVMAX];
@@ -248,7 +319,7 @@ int orc_burn_zone_src(const orc_net *net, double *row, const double *scale, cons
         memcpy(Zs, Z, sizeof(double) * (size_t)(q + 1) * nv);
         predict(nv, q, Z);
 
-        if (newton(&S, q, h, Z, w, rtol, y, dy, st)) {
+        if (newton(&S, &J, q, h, Z, w, y, dy, st)) {
             memcpy(Z, Zs, sizeof(double) * (size_t)(q + 1) * nv);
             st->ncf++;
             if (++ncf >= 10) { status = ORC_CONV; break; }
@@ -342,13 +413,15 @@ int orc_fixed_steps(const orc_net *net, const double *scale, int q, double h, in
     sys_t S = {net, scale, orc_nvar(net), NULL};
     int nv = S.nv;
     orc_stats st;
+    jac_t J;
+    memset(&J, 0, sizeof J);
     double Z[(ORC_QMAX + 2) * ORC_NVMAX], w[ORC_NVMAX], y[ORC_NVMAX], dy[ORC_NVMAX];
     memset(&st, 0, sizeof(st));
     memcpy(Z, Zio, sizeof(double) * (size_t)(q + 1) * nv);
     for (int n = 0; n < nsteps; n++) {
         for (int i = 0; i < nv; i++) w[i] = 1e-12 + 1e-8 * fabs(Z[i]);
         predict(nv, q, Z);
-        if (newton(&S, q, h, Z, w, 1e-8, y, dy, &st)) return n + 1;
+        if (newton(&S, &J, q, h, Z, w, y, dy, &st)) return n + 1;
         if (errs) errs[n] = local_error(nv, q, dy, w);
         correct(nv, q, Z, y, dy);
         for (int i = 0; i < nv; i++) ys[(size_t)n * nv + i] = Z[i];
@@ -379,6 +452,14 @@ int orc_burn_retry(const orc_net *net, double *state, int64_t zones, const doubl
                    const double *source, double dt, double rtol, double atol, int max_steps,
                    const orc_retry *retry, int32_t *status, int32_t *stats, int nthreads)
 {
+    return orc_burn_ex(net, state, zones, scale, source, dt, rtol, atol, max_steps, 0, retry, status,
+                       stats, nthreads);
+}
+
+int orc_burn_ex(const orc_net *net, double *state, int64_t zones, const double *scale,
+                const double *source, double dt, double rtol, double atol, int max_steps,
+                int jac_policy, const orc_retry *retry, int32_t *status, int32_t *stats, int nthreads)
+{
     if (orc_check_net(net)) return -1;
     int row = net->ns + 1;
     int bad = 0;
@@ -390,11 +471,12 @@ int orc_burn_retry(const orc_net *net, double *state, int64_t zones, const doubl
         const double *sc = scale ? scale + z * net->nr : NULL;
         const double *sr = source ? source + z * row : NULL;
         memcpy(in, y, sizeof(double) * row);
-        int s = orc_burn_zone_src(net, y, sc, sr, dt, rtol, atol, max_steps, &st);
+        int s = orc_burn_zone_ex(net, y, sc, sr, dt, rtol, atol, max_steps, jac_policy, &st);
         if (s != ORC_OK && retry && retry->enabled) {
             orc_stats st2;
             memcpy(y, in, sizeof(double) * row);
-            s = orc_burn_zone_src(net, y, sc, sr, dt, retry->rtol, retry->atol, retry->max_steps, &st2);
+            s = orc_burn_zone_ex(net, y, sc, sr, dt, retry->rtol, retry->atol, retry->max_steps,
+                                 jac_policy, &st2);
             if (s == ORC_OK) s = ORC_OK_RETRY;
             st.nst += st2.nst; st.nfe += st2.nfe; st.nje += st2.nje; st.nlu += st2.nlu;
             st.nni += st2.nni; st.netf += st2.netf; st.ncf += st2.ncf;

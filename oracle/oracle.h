@@ -89,4 +89,14 @@ int orc_burn_retry(const orc_net *net, double *state, int64_t zones, const doubl
                    const double *source, double dt, double rtol, double atol, int max_steps,
                    const orc_retry *retry, int32_t *status, int32_t *stats, int nthreads);
 
+/* jac_policy 0: Jacobian and LU on every step attempt (the default everywhere above).
+   jac_policy 1: VODE-style reuse of the iteration matrix and the Jacobian (rules in bdf.c). */
+int orc_burn_zone_ex(const orc_net *net, double *row, const double *scale, const double *src,
+                     double dt, double rtol, double atol, int max_steps, int jac_policy,
+                     orc_stats *st);
+int orc_burn_ex(const orc_net *net, double *state, int64_t zones, const double *scale,
+                const double *source, double dt, double rtol, double atol, int max_steps,
+                int jac_policy, const orc_retry *retry, int32_t *status, int32_t *stats,
+                int nthreads);
+
 #endif

@@ -489,6 +489,58 @@ def test_loose_tolerance_zones_match_scipy_radau():
         assert gated_err(out[k, :14], r.y[:, -1], rtol=1e-6, atol=1e-10) < 1e-4, z
 
 
+# --------------------------------------- VODE-style Jacobian/LU reuse (policy 1)
+
+@pytest.mark.parametrize("seed", range(4))
+def test_reuse_linear_network_matches_matrix_exponential(seed):
+    ns = 4 + seed % 3
+    net = W.linear_network(ns, seed)
+    K = linear_K(net)
+    y0 = np.random.default_rng(seed).dirichlet(np.ones(ns))
+    st = np.zeros((1, ns + 1))
+    st[0, :ns] = y0
+    out, status, stats = oracle.burn(net, st, 10.0, RTOL, ATOL, jac_policy=1)
+    assert status[0] == 0
+    assert gated_err(out[0, :ns], sla.expm(K * 10.0) @ y0) < 1e-6
+    assert stats[0, 2] < stats[0, 0]            # fewer Jacobians than steps
+
+
+def test_reuse_closed_forms_and_invariants():
+    k, ya, yb, dt = 5.0, 0.6, 0.25, 2.0
+    out, status, _ = oracle.burn(W.two_body_network(k), np.array([[ya, yb, 0.05, 0.1, 0.0]]), dt,
+                                 RTOL, ATOL, jac_policy=1)
+    d = ya - yb
+    YB = d * yb / (ya * math.exp(k * d * dt) - yb)
+    assert status[0] == 0 and gated_err(out[0, :4], [YB + d, YB, 0.05 + (yb - YB), 0.1 + (yb - YB)]) < 1e-6
+    c2 = W.config2(32)
+    out, status, _ = oracle.burn(c2["net"], c2["state"], 1.0, RTOL, ATOL, jac_policy=1)
+    assert np.all(status == 0)
+    assert np.abs(out[:, :13].sum(1) - c2["state"][:, :13].sum(1)).max() < 1e-12
+    net, B = W.energy_test_network(8, 20, seed=4)
+    st = W.random_zones(net, 8, seed=3, T_range=(500, 900))
+    out, status, _ = oracle.burn(net, st, 1.0, RTOL, ATOL, jac_policy=1)
+    assert np.all(status == 0)
+    e0, e1 = st[:, -1] + st[:, :-1] @ B, out[:, -1] + out[:, :-1] @ B
+    assert np.abs(e1 - e0).max() < 1e-11 * np.abs(e0).max()
+
+
+def test_reuse_robertson_and_benchmark_zones_match_scipy_radau():
+    net = oracle.Net(W.robertson_network())
+    sol = solve_ivp(lambda t, y: oracle.rhs(net, y), (0, 1e5), [1.0, 0.0, 0.0], method="Radau",
+                    rtol=1e-12, atol=1e-20, jac=lambda t, y: oracle.jac(net, y))
+    out, status, stats = oracle.burn(net, np.array([[1.0, 0.0, 0.0, 0.0]]), 1e5, RTOL, ATOL,
+                                     jac_policy=1)
+    assert status[0] == 0 and gated_err(out[0, :3], sol.y[:, -1]) < 1e-6
+    assert stats[0, 2] * 4 < stats[0, 0]
+    c2 = W.config2(96)
+    for z in (3, 43):
+        r = solve_ivp(lambda t, y: oracle.rhs(c2["net"], y), (0.0, 1.0), c2["state"][z, :14],
+                      method="Radau", rtol=1e-12, atol=1e-20, jac=lambda t, y: oracle.jac(c2["net"], y))
+        out, status, stats = oracle.burn(c2["net"], c2["state"][z:z + 1], 1.0, RTOL, ATOL, jac_policy=1)
+        assert status[0] == 0 and gated_err(out[0, :14], r.y[:, -1]) < 1e-5, z
+        assert stats[0, 2] * 5 < stats[0, 0] and stats[0, 3] * 5 < stats[0, 0]
+
+
 # ------------------------------------------------------- zone-by-zone retry
 
 def test_retry_reruns_failed_zones_from_their_input():
