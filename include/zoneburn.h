@@ -76,6 +76,7 @@ typedef struct zb_server zb_server;
 
 enum { ZB_FP64 = 0, ZB_MIXED = 1 };               /* zb_opts.precision */
 enum { ZB_MAP_AUTO = 0 };                          /* zb_opts.mapping: else lanes per zone 1..64 */
+enum { ZB_JAC_EVERY_STEP = 0, ZB_JAC_REUSE = 1 };  /* zb_opts.jac_policy */
 
 typedef struct {
     int32_t max_steps;   /* accepted steps per zone before ZB_ZONE_MAXSTEPS (<= 0: 100000) */
@@ -91,7 +92,16 @@ typedef struct {
                             its counters add up over both runs.  0: off */
     double retry_rtol, retry_atol;   /* > 0 when retry is on */
     int32_t retry_max_steps;         /* <= 0: the same as max_steps */
-    int32_t reserved;
+    int32_t jac_policy;  /* ZB_JAC_EVERY_STEP (0): Jacobian and LU on every step attempt.
+                            ZB_JAC_REUSE (1): the VODE-style reuse (the integrator the paper
+                            names, Brown-Byrne-Hindmarsh 1989): the factored iteration matrix is
+                            kept across steps and re-formed when gamma = h l_0 moved by more than
+                            30 % since it was factored, after 20 steps, or after a Newton failure
+                            with a Jacobian from an earlier step (then J is refreshed at the same
+                            prediction and Newton retried once); a re-formed matrix takes a fresh
+                            J unless the saved one is younger than 50 steps and gamma moved by
+                            less than 20 %; a lagged matrix's correction is scaled by
+                            2 / (1 + gamma / gamma_M).  The Jacobian stays in the zone's LDS. */
 } zb_opts;
 
 /* Create a context on HIP device `device` (allocates a small device workspace). */

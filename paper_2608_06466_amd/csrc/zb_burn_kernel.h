@@ -295,6 +295,15 @@ __device__ __forceinline__ T gbcast_solve(T v, bool owner, double *slot)
     else return gbcast<L>(v, owner);
 }
 
+// A group-uniform flag, stated as such for whole-wave groups (so code under it may keep
+// wave-uniform values in scalar registers).
+template <int L>
+__device__ __forceinline__ bool group_uniform(bool b)
+{
+    if constexpr (L == 64) return __builtin_amdgcn_readfirstlane((int)b) != 0;
+    else return b;
+}
+
 template <int L>
 __device__ __forceinline__ bool gany(bool b)
 {
@@ -384,6 +393,10 @@ struct Zone {
     double src[RPL];            // constant source of the zone (0 without one)
     double rtol, atol;          // tolerances of the current run (the retry may loosen them)
     int max_steps, tries;
+    // iteration-matrix state for the VODE-style reuse (jac_policy 1)
+    double gamma_m;             // gamma the factors in M were formed with
+    double cs[RPL];             // column scale of the factors (mixed: the error weight then)
+    int have_j, have_m, nst_j, nst_m;
     LT M[RPL][NVP];             // iteration matrix rows, then their LU factors
     LT dinv[RPL];               // 1 / pivot of the row (valid once it is a pivot row)
     LT rs[RPL];                 // row scaling of the FP32 LU
@@ -407,6 +420,7 @@ struct Ctx {
     int32_t *status, *stats;
     double rtol, atol, dt;
     int64_t zone;
+    int jac_policy;
 };
 
 template <int NVP, int L>
@@ -436,7 +450,7 @@ __device__ __forceinline__ double wrms(const Ctx &c, const Zone<NVP, L, LT> &z,
 // its FP32 scaling) in registers.  y and f are by local row.
 template <bool WANTJ, int NVP, int L, class LT>
 __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const double (&yv)[Zone<NVP, L, LT>::RPL],
-                     double (&fo)[Zone<NVP, L, LT>::RPL], double gamma)
+                     double (&fo)[Zone<NVP, L, LT>::RPL])
 {
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
     const DevNet &N = c.net;
@@ -556,37 +570,52 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
         fo[s] = fi + z.src[s];
     }
 
-    if (WANTJ) {
-        lds_fence();
-        constexpr bool MIXED = sizeof(LT) == 4;
-        const double *wb = c.S + c.lay.wbuf;
-        sfor<0, RPL>([&](auto S) {
-            int i = row_of<NVP, L>(c, S);
-            double rmax = 0.0;
-            double mrow[NVP];
-            if (i < N.nv) {
-                sfor<0, NVP>([&](auto J) {
-                    double m = (J == i ? 1.0 : 0.0) - gamma * jb[i * JS + J];
-                    if (J >= N.nv) m = (J == i) ? 1.0 : 0.0;
-                    if (MIXED) {
-                        m *= wb[J];
-                        rmax = fmax(rmax, fabs(m));
-                    }
-                    mrow[J] = m;
-                });
-            } else {
-                sfor<0, NVP>([&](auto J) { mrow[J] = (J == i) ? 1.0 : 0.0; });
-                rmax = 1.0;
-            }
-            if (MIXED) {
-                double sc = rmax > 0.0 ? 1.0 / rmax : 1.0;
-                z.rs[S] = (LT)sc;
-                sfor<0, NVP>([&](auto J) { z.M[S][J] = (LT)(mrow[J] * sc); });
-            } else {
-                sfor<0, NVP>([&](auto J) { z.M[S][J] = (LT)mrow[J]; });
-            }
-        });
-    }
+}
+
+// M = I - gamma J from the Jacobian rows in LDS (left there by eval<true>), in
+// registers.  The mixed path scales column j by the error weight w_j and the row by
+// 1 / max; the column scales in force are kept per zone for the solves, since a matrix
+// may be reused at later steps.
+template <int NVP, int L, class LT>
+__device__ __forceinline__ void form_M(const Ctx &c, Zone<NVP, L, LT> &z, double gamma)
+{
+    constexpr int RPL = Zone<NVP, L, LT>::RPL;
+    constexpr int JS = NVP + 1;
+    const DevNet &N = c.net;
+    const double *jb = c.S + c.lay.jbuf;
+    lds_fence();
+    constexpr bool MIXED = sizeof(LT) == 4;
+    const double *wb = c.S + c.lay.wbuf;
+    sfor<0, RPL>([&](auto S) {
+        int i = row_of<NVP, L>(c, S);
+        double rmax = 0.0;
+        double mrow[NVP];
+        if (i < N.nv) {
+            sfor<0, NVP>([&](auto J) {
+                double m = (J == i ? 1.0 : 0.0) - gamma * jb[i * JS + J];
+                if (J >= N.nv) m = (J == i) ? 1.0 : 0.0;
+                if (MIXED) {
+                    m *= wb[J];
+                    rmax = fmax(rmax, fabs(m));
+                }
+                mrow[J] = m;
+            });
+        } else {
+            sfor<0, NVP>([&](auto J) { mrow[J] = (J == i) ? 1.0 : 0.0; });
+            rmax = 1.0;
+        }
+        if (MIXED) {
+            double sc = rmax > 0.0 ? 1.0 / rmax : 1.0;
+            z.rs[S] = (LT)sc;
+            sfor<0, NVP>([&](auto J) { z.M[S][J] = (LT)(mrow[J] * sc); });
+        } else {
+            sfor<0, NVP>([&](auto J) { z.M[S][J] = (LT)mrow[J]; });
+        }
+    });
+    sfor<0, RPL>([&](auto S) {
+        const int i = row_of<NVP, L>(c, S);
+        z.cs[S] = (i < NVP) ? c.S[c.lay.wbuf + i] : 1.0;
+    });
 }
 
 // --------------------------------------------------------------- LU / solve
@@ -722,7 +751,7 @@ __device__ __forceinline__ void lu_solve(const Ctx &c, const Zone<NVP, L, LT> &z
             if (after(c.gl, v) < k) v = fma(-z.M[0][k], xk, v);
         });
         double x = c.gl < nv ? (double)(v * z.dinv[0]) : 0.0;
-        if (MIXED && c.gl < NVP) x *= c.S[c.lay.wbuf + c.gl];
+        if (MIXED) x *= z.cs[0];
         b[0] = x;
         return;
     }
@@ -764,13 +793,9 @@ __device__ __forceinline__ void lu_solve(const Ctx &c, const Zone<NVP, L, LT> &z
         });
         if (c.gl == (k % L)) x[k / L] = xk;
     });
-    const double *wb = c.S + c.lay.wbuf;
     sfor<0, RPL>([&](auto S) {
         double v = (double)x[S];
-        if (MIXED) {
-            int i = row_of<NVP, L>(c, S);
-            if (i < NVP) v *= wb[i];
-        }
+        if (MIXED) v *= z.cs[S];
         b[S] = v;
     });
 }
@@ -861,11 +886,14 @@ __device__ __forceinline__ int zone_start(const Ctx &c, Zone<NVP, L, LT> &z)
     }
     z.nst = z.nje = z.nlu = z.nni = z.netf = z.ncf = 0;
     z.nfe = 0;
+    z.have_j = z.have_m = 0;
+    z.nst_j = z.nst_m = 0;
+    z.gamma_m = 1.0;
     lds_fence();
     if (gany<L>(bad)) return ZB_ZONE_NONFINITE;
     set_weights(c, z);
     double f0[RPL], y1[RPL], f1[RPL];
-    eval<false>(c, z, z.Z[0], f0, 0.0);
+    eval<false>(c, z, z.Z[0], f0);
     z.nfe = 1;
     bool badf = false;
 #pragma unroll
@@ -877,7 +905,7 @@ __device__ __forceinline__ int zone_start(const Ctx &c, Zone<NVP, L, LT> &z)
     double ha = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
 #pragma unroll
     for (int s = 0; s < RPL; ++s) y1[s] = z.Z[0][s] + ha * f0[s];
-    eval<false>(c, z, y1, f1, 0.0);
+    eval<false>(c, z, y1, f1);
     z.nfe = 2;
 #pragma unroll
     for (int s = 0; s < RPL; ++s) y1[s] = f1[s] - f0[s];
@@ -896,6 +924,54 @@ __device__ __forceinline__ int zone_start(const Ctx &c, Zone<NVP, L, LT> &z)
 }
 
 // One step attempt.  Returns RUNNING, or the zone's final status.
+// Newton iterations on the corrector with the current factors; z.f holds f at the
+// prediction.  With factors formed at another gamma the correction is scaled by
+// 2 / (1 + gamma / gamma_M).  Returns whether the iteration converged.
+template <int NVP, int L, class LT>
+__device__ __forceinline__ bool newton(const Ctx &c, Zone<NVP, L, LT> &z, double l0, double h, double tau)
+{
+    constexpr int RPL = Zone<NVP, L, LT>::RPL;
+    const double rc = h * l0 / z.gamma_m;
+    const double cscale = (rc != 1.0) ? 2.0 / (1.0 + rc) : 1.0;
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        z.y[s] = z.Z[0][s];
+        z.dy[s] = 0.0;
+    }
+    double dprev = 0.0;
+    for (int m = 0; m < 4; ++m) {
+        if (m > 0) {
+            eval<false>(c, z, z.y, z.f);
+            z.nfe++;
+        }
+        double b[RPL];
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) b[s] = -(z.dy[s] - l0 * (h * z.f[s] - z.Z[1][s]));
+        lu_solve(c, z, b);
+        if (cscale != 1.0) {
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) b[s] *= cscale;
+        }
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) {
+            z.y[s] += b[s];
+            z.dy[s] += b[s];
+        }
+        double d = wrms(c, z, b);
+        z.nni++;
+        if (!isfinite(d)) return false;
+        if (m == 0) {
+            if (d <= tau) return true;
+        } else {
+            double rho = d / dprev;
+            if (rho < 1.0 && rho * d / (1.0 - rho) <= tau) return true;
+            if (rho >= 1.0 || pow(rho, (double)(4 - m)) * d / (1.0 - rho) > tau) return false;
+        }
+        dprev = d;
+    }
+    return false;
+}
+
 template <int NVP, int L, class LT>
 __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
 {
@@ -923,46 +999,39 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
 
     const double l0 = 1.0 / harmonic(z.q);
     const double h = z.h;
-    // Jacobian and f at the prediction, LU
-    eval<true>(c, z, z.Z[0], z.f, h * l0);
-    z.nfe++;
-    z.nje++;
-    z.nlu++;
-    lu_factor(c, z);
-
-    // Newton
-#pragma unroll
-    for (int s = 0; s < RPL; ++s) {
-        z.y[s] = z.Z[0][s];
-        z.dy[s] = 0.0;
-    }
-    bool conv = false;
-    double dprev = 0.0;
-    for (int m = 0; m < 4; ++m) {
-        if (m > 0) {
-            eval<false>(c, z, z.y, z.f, 0.0);
-            z.nfe++;
+    const double gamma = h * l0;
+    // f at the prediction, and the iteration matrix: formed on every attempt (policy 0),
+    // or kept across steps and re-formed by the VODE rules (policy 1).  A second pass,
+    // policy 1 only, refreshes a Jacobian from an earlier step after a Newton failure.
+    // (Whole-wave zones take these branches uniformly; the compiler is told so.)
+    bool conv = false, fresh = false;
+    for (int pass = 0; pass < 2; ++pass) {
+        bool new_j = true, new_m = true;
+        if (c.jac_policy != 0 && pass == 0) {
+            const double drc = z.have_m ? fabs(gamma / z.gamma_m - 1.0) : 1.0;
+            new_m = group_uniform<L>(!z.have_m || drc > 0.3 || z.nst >= z.nst_m + 20);
+            new_j = group_uniform<L>(new_m && (!z.have_j || z.nst >= z.nst_j + 50 || drc >= 0.2));
         }
-        double b[RPL];
-#pragma unroll
-        for (int s = 0; s < RPL; ++s) b[s] = -(z.dy[s] - l0 * (h * z.f[s] - z.Z[1][s]));
-        lu_solve(c, z, b);
-#pragma unroll
-        for (int s = 0; s < RPL; ++s) {
-            z.y[s] += b[s];
-            z.dy[s] += b[s];
-        }
-        double d = wrms(c, z, b);
-        z.nni++;
-        if (!isfinite(d)) break;
-        if (m == 0) {
-            if (d <= tau) { conv = true; break; }
+        if (new_j) {
+            eval<true>(c, z, z.Z[0], z.f);
+            z.nje++;
+            z.have_j = 1;
+            z.nst_j = z.nst;
+            fresh = true;
         } else {
-            double rho = d / dprev;
-            if (rho < 1.0 && rho * d / (1.0 - rho) <= tau) { conv = true; break; }
-            if (rho >= 1.0 || pow(rho, (double)(4 - m)) * d / (1.0 - rho) > tau) break;
+            eval<false>(c, z, z.Z[0], z.f);
         }
-        dprev = d;
+        z.nfe++;
+        if (new_m) {
+            form_M(c, z, gamma);
+            lu_factor(c, z);
+            z.nlu++;
+            z.gamma_m = gamma;
+            z.have_m = 1;
+            z.nst_m = z.nst;
+        }
+        conv = newton(c, z, l0, h, tau);
+        if (group_uniform<L>(conv || c.jac_policy == 0 || fresh)) break;
     }
 
     if (!conv) {
@@ -1003,7 +1072,7 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
         if (z.nefc >= 3) {
             z.q = 1;
             double f0[RPL];
-            eval<false>(c, z, z.Z[0], f0, 0.0);
+            eval<false>(c, z, z.Z[0], f0);
             z.nfe++;
 #pragma unroll
             for (int s = 0; s < RPL; ++s) z.Z[1][s] = z.h * f0[s];
@@ -1200,12 +1269,16 @@ __device__ __forceinline__ void load_segment(Ctx &c, const BurnArgs &A, int seg,
 // SIMD; bounding them to two waves costs a few spilled registers and is ~20 %
 // faster (the LU and solve chains are latency-bound).  The smaller kernels are
 // left to the compiler (a bound there only adds spills).
-template <int NVP, int L>
-constexpr int min_waves_per_eu() { return (NVP >= 48 && L == 64) ? 2 : 1; }
+template <int NVP, int L, int JP>
+constexpr int min_waves_per_eu()
+{
+    // the reuse kernels keep the factors live across steps: bounded to two waves too
+    return ((NVP >= 48 && L == 64) || (JP == 1 && L >= 16)) ? 2 : 1;
+}
 
-template <int NVP, int L, class LT>
+template <int NVP, int L, class LT, int JP>
 __global__ __launch_bounds__(64)
-__attribute__((amdgpu_waves_per_eu(min_waves_per_eu<NVP, L>())))
+__attribute__((amdgpu_waves_per_eu(min_waves_per_eu<NVP, L, JP>())))
 void burn_kernel(BurnArgs A)
 {
     extern __shared__ double smem[];
@@ -1216,6 +1289,8 @@ void burn_kernel(BurnArgs A)
     const int g = lane / L;
     Zone<NVP, L, LT> z;
     int seg = 0;
+    c.jac_policy = JP;   // a constant: each policy is its own kernel (the reuse keeps the
+                         // factors live across steps, which costs registers)
     load_segment(c, A, seg, NVP, L * RPL);
     c.S = smem + g * c.lay.total;
     int64_t zones = uniform(A.seg[0].zones);
@@ -1280,6 +1355,7 @@ void burn_kernel(BurnArgs A)
     }
 }
 
-#define ZB_K(NVP, L, LT, MIX) {NVP, L, MIX, (const void *)&burn_kernel<NVP, L, LT>}
+#define ZB_K(NVP, L, LT, MIX) {NVP, L, MIX, 0, (const void *)&burn_kernel<NVP, L, LT, 0>}
+#define ZB_KR(NVP, L, LT, MIX) {NVP, L, MIX, 1, (const void *)&burn_kernel<NVP, L, LT, 1>}
 
 }  // namespace zb

@@ -200,13 +200,14 @@ static int default_lanes(int nv)
 }
 
 // Smallest kernel with nvp >= nv for the given lanes and precision.
-const KernelInfo *zbh::find_kernel(int nv, int lanes, int mixed)
+const KernelInfo *zbh::find_kernel(int nv, int lanes, int mixed, int jac)
 {
     const KernelInfo *tab;
     int n = kernel_table(&tab);
     const KernelInfo *best = nullptr;
     for (int i = 0; i < n; ++i) {
-        if (tab[i].lanes != lanes || tab[i].mixed != mixed || tab[i].nvp < nv) continue;
+        if (tab[i].lanes != lanes || tab[i].mixed != mixed || tab[i].jac != jac || tab[i].nvp < nv)
+            continue;
         if (!best || tab[i].nvp < best->nvp) best = &tab[i];
     }
     return best;
@@ -282,15 +283,16 @@ int zbh::blocks_per_cu(const KernelInfo *k, int max_nr)
 // MAXSEG device counters the launch clears first; nfail: failed-zone counter.
 namespace {
 struct RunOpts {
-    int max_steps, retry, retry_max_steps;
+    int max_steps, retry, retry_max_steps, jac_policy;
     double retry_rtol, retry_atol;
 };
 }  // namespace
 
 static RunOpts run_opts(const zb_opts *o)
 {
-    RunOpts r{100000, 0, 100000, 0.0, 0.0};
+    RunOpts r{100000, 0, 100000, 0, 0.0, 0.0};
     if (o && o->max_steps > 0) r.max_steps = o->max_steps;
+    if (o) r.jac_policy = o->jac_policy;
     if (o && o->retry) {
         r.retry = 1;
         r.retry_rtol = o->retry_rtol;
@@ -383,6 +385,9 @@ static zb_err plan_groups(zb_context *ctx, const zb_segment *segs, int n, const 
         !(isfinite(opts->retry_rtol) && opts->retry_rtol > 0.0 && isfinite(opts->retry_atol) &&
           opts->retry_atol > 0.0))
         return fail(ZB_EINVAL, "retry needs finite retry_rtol > 0 and retry_atol > 0");
+    if (opts && opts->jac_policy != ZB_JAC_EVERY_STEP && opts->jac_policy != ZB_JAC_REUSE)
+        return fail(ZB_EINVAL, "jac_policy %d", opts->jac_policy);
+    const int jac = opts ? opts->jac_policy : 0;
     for (int i = 0; i < n; ++i) {
         zb_err e = check_segment(ctx, segs[i]);
         if (e != ZB_OK) return e;
@@ -391,7 +396,7 @@ static zb_err plan_groups(zb_context *ctx, const zb_segment *segs, int n, const 
     for (int i = 0; i < n; ++i) {
         if (segs[i].zones == 0) continue;
         int lanes = force_lanes ? force_lanes : lanes_for(ctx, segs[i].net, prec, opts);
-        const KernelInfo *k = find_kernel(segs[i].net->dn.nv, lanes, prec == ZB_MIXED);
+        const KernelInfo *k = find_kernel(segs[i].net->dn.nv, lanes, prec == ZB_MIXED, jac);
         if (!k)
             return fail(ZB_EUNSUPPORTED, "no kernel for nv=%d with %d lanes per zone (%s)",
                         segs[i].net->dn.nv, lanes, prec == ZB_MIXED ? "mixed" : "fp64");
@@ -624,7 +629,7 @@ extern "C" zb_err zb_autotune(zb_context *ctx, const zb_network *net, const doub
     zb_err res = ZB_OK;
     for (int li = 0, lanes = 1; lanes <= 64; ++li, lanes *= 2) {
         if (times_ms) times_ms[li] = -1.f;
-        if (!find_kernel(net->dn.nv, lanes, precision == ZB_MIXED)) continue;
+        if (!find_kernel(net->dn.nv, lanes, precision == ZB_MIXED, 0)) continue;
         zb_segment s = {net, work, zones, dt, rtol, atol, nullptr, st, nullptr};
         float ms = 0.f;
         for (int rep = 0; rep < 2; ++rep) {   // the first launch also loads the code object

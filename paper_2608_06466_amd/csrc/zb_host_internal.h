@@ -48,7 +48,7 @@ struct Workspace {
     unsigned long long *nfail;
 };
 
-const zb::KernelInfo *find_kernel(int nv, int lanes, int mixed);
+const zb::KernelInfo *find_kernel(int nv, int lanes, int mixed, int jac);
 int lanes_for(zb_context *ctx, const zb_network *net, int prec, const zb_opts *o);
 zb_err check_segment(zb_context *ctx, const zb_segment &s);
 // Validates the segments and launches them (one persistent launch per kernel

@@ -84,6 +84,7 @@ struct KernelInfo {
     int nvp;          // padded number of variables the kernel handles (nv <= nvp)
     int lanes;        // lanes per zone
     int mixed;        // 0: FP64 LU, 1: FP32 LU
+    int jac;          // jac_policy the kernel implements (0 every step, 1 reuse)
     const void *fn;   // __global__ function
 };
 

@@ -14,6 +14,12 @@ int kernels_24(const KernelInfo **out);
 int kernels_32(const KernelInfo **out);
 int kernels_48d(const KernelInfo **out);
 int kernels_48f(const KernelInfo **out);
+int kernels_04r(const KernelInfo **out);
+int kernels_16r(const KernelInfo **out);
+int kernels_24r(const KernelInfo **out);
+int kernels_32r(const KernelInfo **out);
+int kernels_48dr(const KernelInfo **out);
+int kernels_48fr(const KernelInfo **out);
 
 __global__ void reset_kernel(unsigned long long *p, int n)
 {
@@ -43,6 +49,12 @@ int kernel_table(const KernelInfo **out)
         add(kernels_32);
         add(kernels_48d);
         add(kernels_48f);
+        add(kernels_04r);
+        add(kernels_16r);
+        add(kernels_24r);
+        add(kernels_32r);
+        add(kernels_48dr);
+        add(kernels_48fr);
         return t;
     }();
     *out = table.data();

@@ -387,6 +387,8 @@ extern "C" zb_err zb_server_create(zb_context *ctx, const zb_server_opts *so, zb
     if (bo.retry && !(isfinite(bo.retry_rtol) && bo.retry_rtol > 0.0 && isfinite(bo.retry_atol) &&
                       bo.retry_atol > 0.0))
         return fail(ZB_EINVAL, "retry needs finite retry_rtol > 0 and retry_atol > 0");
+    if (bo.jac_policy != ZB_JAC_EVERY_STEP && bo.jac_policy != ZB_JAC_REUSE)
+        return fail(ZB_EINVAL, "jac_policy %d", bo.jac_policy);
     DeviceGuard g(ctx->device);
     zb_server *S = new (std::nothrow) zb_server();
     if (!S) return fail(ZB_ENOMEM, "host allocation failed");
@@ -439,7 +441,7 @@ extern "C" zb_err zb_server_submit(zb_server *S, const zb_network *net, const do
         return fail(ZB_EINVAL, "dt, rtol and atol must be finite and > 0");
     const int row = net->dn.ns + 1;
     const int lanes = lanes_for(S->ctx, net, S->opts.precision, &S->opts);
-    const KernelInfo *k = find_kernel(net->dn.nv, lanes, S->opts.precision == ZB_MIXED);
+    const KernelInfo *k = find_kernel(net->dn.nv, lanes, S->opts.precision == ZB_MIXED, S->opts.jac_policy);
     if (!k) return fail(ZB_EUNSUPPORTED, "no kernel for nv=%d with %d lanes", net->dn.nv, lanes);
     auto al = [](size_t b) { return (b + ALIGN - 1) & ~(ALIGN - 1); };
     size_t bytes = al(sizeof(double) * row * (size_t)zones) + al(sizeof(int32_t) * (size_t)zones) +

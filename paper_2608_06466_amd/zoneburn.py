@@ -39,7 +39,7 @@ class _Desc(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("max_steps", C.c_int32), ("precision", C.c_int32), ("mapping", C.c_int32),
                 ("retry", C.c_int32), ("retry_rtol", C.c_double), ("retry_atol", C.c_double),
-                ("retry_max_steps", C.c_int32), ("reserved", C.c_int32)]
+                ("retry_max_steps", C.c_int32), ("jac_policy", C.c_int32)]
 
 
 class _Segment(C.Structure):
@@ -177,13 +177,18 @@ class Network:
             pass
 
 
-def _opts(precision, lanes, max_steps, retry=None):
-    """retry: None, or (rtol, atol, max_steps) of the zone-by-zone retry of failed zones."""
+JAC_EVERY_STEP, JAC_REUSE = 0, 1
+
+
+def _opts(precision, lanes, max_steps, retry=None, jac_policy=0):
+    """retry: None, or (rtol, atol, max_steps) of the zone-by-zone retry of failed zones.
+    jac_policy: 0 Jacobian and LU every step attempt, 1 VODE-style reuse."""
     prec = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}[precision]
+    jp = {"every_step": 0, "reuse": 1, 0: 0, 1: 1}[jac_policy]
     if retry is None:
-        return _Opts(int(max_steps or 0), prec, int(lanes or 0), 0, 0.0, 0.0, 0, 0)
+        return _Opts(int(max_steps or 0), prec, int(lanes or 0), 0, 0.0, 0.0, 0, jp)
     return _Opts(int(max_steps or 0), prec, int(lanes or 0), 1, float(retry[0]), float(retry[1]),
-                 int(retry[2]), 0)
+                 int(retry[2]), jp)
 
 
 def _check_state(net, state):
@@ -194,7 +199,8 @@ def _check_state(net, state):
 
 
 def burn(ctx, net, state, dt, rtol, atol, rate_scale=None, precision="fp64", lanes=0,
-         max_steps=0, want_status=True, want_stats=True, stream=None, source=None, retry=None):
+         max_steps=0, want_status=True, want_stats=True, stream=None, source=None, retry=None,
+         jac_policy=0):
     """In-place burn of state [zones][ns+1]; returns (status int32[zones], stats int32[zones,7]).
 
     source: optional constant per-zone term [zones][ns+1] added to the right-hand side
@@ -207,7 +213,8 @@ def burn(ctx, net, state, dt, rtol, atol, rate_scale=None, precision="fp64", lan
         stats = torch.empty((zones, 7), dtype=torch.int32, device=state.device) if want_stats else None
         burn_batch(ctx, [dict(net=net, state=state, dt=dt, rtol=rtol, atol=atol, rate_scale=rate_scale,
                               status=status, stats=stats, source=source)],
-                   precision=precision, lanes=lanes, max_steps=max_steps, stream=stream, retry=retry)
+                   precision=precision, lanes=lanes, max_steps=max_steps, stream=stream, retry=retry,
+                   jac_policy=jac_policy)
         return status, stats
     zones = state.shape[0]
     if rate_scale is not None and (rate_scale.dtype != torch.float64 or not rate_scale.is_cuda
@@ -216,7 +223,7 @@ def burn(ctx, net, state, dt, rtol, atol, rate_scale=None, precision="fp64", lan
         raise ValueError("rate_scale must be a contiguous float64 CUDA tensor [zones][R]")
     status = torch.empty(zones, dtype=torch.int32, device=state.device) if want_status else None
     stats = torch.empty((zones, 7), dtype=torch.int32, device=state.device) if want_stats else None
-    o = _opts(precision, lanes, max_steps, retry)
+    o = _opts(precision, lanes, max_steps, retry, jac_policy)
     _check(lib().zb_burn(ctx.h, net.h, _ptr(state), zones, float(dt), float(rtol), float(atol),
                          _ptr(rate_scale), C.byref(o), _ptr(status), _ptr(stats),
                          _stream_handle(stream)), "zb_burn")
@@ -246,11 +253,12 @@ def _segments(segments):
     return arr
 
 
-def burn_batch(ctx, segments, precision="fp64", lanes=0, max_steps=0, stream=None, retry=None):
+def burn_batch(ctx, segments, precision="fp64", lanes=0, max_steps=0, stream=None, retry=None,
+               jac_policy=0):
     """segments: list of dicts(net, state, dt, rtol, atol, rate_scale=None, status=None,
     stats=None, source=None); retry: None or (rtol, atol, max_steps)."""
     arr = _segments(segments)
-    o = _opts(precision, lanes, max_steps, retry)
+    o = _opts(precision, lanes, max_steps, retry, jac_policy)
     _check(lib().zb_burn_batch(ctx.h, arr, len(segments), C.byref(o), _stream_handle(stream)),
            "zb_burn_batch")
 
@@ -258,11 +266,12 @@ def burn_batch(ctx, segments, precision="fp64", lanes=0, max_steps=0, stream=Non
 class Graph:
     """A burn of fixed buffers captured once as a HIP graph (zb_graph_*); launch() replays it."""
 
-    def __init__(self, ctx, segments, precision="fp64", lanes=0, max_steps=0, retry=None):
+    def __init__(self, ctx, segments, precision="fp64", lanes=0, max_steps=0, retry=None,
+                 jac_policy=0):
         self.ctx = ctx
         self._segs = segments          # the buffers must outlive the graph
         arr = _segments(segments)
-        o = _opts(precision, lanes, max_steps, retry)
+        o = _opts(precision, lanes, max_steps, retry, jac_policy)
         h = C.c_void_p()
         _check(lib().zb_graph_create(ctx.h, arr, len(segments), C.byref(o), C.byref(h)),
                "zb_graph_create")
@@ -287,10 +296,11 @@ class Server:
     """Continuous-batching burn server (zb_server_*): host inputs in, host results out."""
 
     def __init__(self, ctx, hbm_budget_bytes, precision="fp64", lanes=0, max_steps=0, streams=0,
-                 launches_per_stream=0, slice_zones=0, max_pending=0, retry=None):
+                 launches_per_stream=0, slice_zones=0, max_pending=0, retry=None, jac_policy=0):
         self.ctx = ctx
         o = _ServerOpts(int(hbm_budget_bytes), int(streams), int(launches_per_stream),
-                        int(slice_zones), int(max_pending), 0, _opts(precision, lanes, max_steps, retry))
+                        int(slice_zones), int(max_pending), 0,
+                        _opts(precision, lanes, max_steps, retry, jac_policy))
         h = C.c_void_p()
         _check(lib().zb_server_create(ctx.h, C.byref(o), C.byref(h)), "zb_server_create")
         self.h = h

@@ -410,3 +410,34 @@ def test_zone_retry_parity(zbm, precision):
         check(f"retry {precision} {'retried' if rt > 1e-8 else 'first run'}", g, (r, fine), rt, at,
               14, gfine)
     net.close()
+
+
+@pytest.mark.parametrize("which", ["config2", "nv22", "nv48"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_jacobian_reuse_parity(zbm, which, precision):
+    """The VODE-style reuse (jac_policy 1) against the oracle's: same statuses, results within
+    the widened bar, and Jacobian/LU counts far below the step counts on both sides."""
+    zb, ctx = zbm
+    if which == "config2":
+        net_d, n, Tr, Td = W.config2_network(), 400, (1e3, 5e3), "uniform"
+    else:
+        k = {"nv22": 1, "nv48": 2}[which]
+        ns, R, seed = W.CONFIG3_NETS[k]
+        net_d, n, Tr, Td = W.random_network(ns, R, seed), [0, 200, 96][k], W.CONFIG3_T_RANGE, "loguniform"
+    st = W.random_zones(net_d, n, seed=777, T_range=Tr, T_dist=Td)
+    ref = oracle.burn(net_d, st, 1.0, 1e-8, 1e-12, jac_policy=1)
+    fine = oracle.burn(net_d, st, 1.0, 1e-10, 1e-14, jac_policy=1, max_steps=10000000)
+    net = zb.Network(ctx, net_d)
+    out = []
+    for rt, at, ms in ((1e-8, 1e-12, 0), (1e-10, 1e-14, 10000000)):
+        t = torch.tensor(st, device="cuda:0")
+        status, stats = zb.burn(ctx, net, t, 1.0, rt, at, precision=precision, jac_policy=1,
+                                max_steps=ms)
+        zb.sync(ctx)
+        out.append((t.cpu().numpy(), status.cpu().numpy(), stats.cpu().numpy()))
+    nv = net_d["n_species"] + 1
+    check(f"{which} reuse {precision}", out[0], (ref, fine), 1e-8, 1e-12, nv, out[1])
+    ok = out[0][1] == 0
+    for s in (out[0][2][ok], ref[2][ok]):
+        assert s[:, 2].sum() * 4 < s[:, 0].sum() and s[:, 3].sum() * 3 < s[:, 0].sum()
+    net.close()
