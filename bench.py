@@ -97,7 +97,7 @@ def headline(args):
     work = torch.empty_like(state0)
     stream = torch.cuda.current_stream()
 
-    def run(precision, steps, warmup):
+    def run(precision, steps, warmup, jac_policy=0):
         lanes = zb.get_mapping(ctx, net, precision)
         times, kernel_ms = [], []
         status = stats = None
@@ -108,7 +108,8 @@ def headline(args):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            status, stats = zb.burn(ctx, net, work, dt, rtol, atol, precision=precision)
+            status, stats = zb.burn(ctx, net, work, dt, rtol, atol, precision=precision,
+                                    jac_policy=jac_policy)
             e1.record(stream)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -116,7 +117,7 @@ def headline(args):
             if it >= warmup:
                 times.append(t1 - t0)
                 kernel_ms.append(e0.elapsed_time(e1))
-            print(f"[bench] {precision} step {it - warmup if it >= warmup else 'warmup'}: "
+            print(f"[bench] {precision} jac {jac_policy} step {it - warmup if it >= warmup else 'warmup'}: "
                   f"{(t1 - t0) * 1e3:.1f} ms (kernel {e0.elapsed_time(e1):.1f} ms), failed zones {nfail}",
                   file=sys.stderr, flush=True)
         st = stats.cpu().numpy()
@@ -127,6 +128,9 @@ def headline(args):
     res = {}
     for prec in ("mixed", "fp64"):
         res[prec] = run(prec, args.steps, args.warmup)
+    # the VODE-style Jacobian/LU reuse (reported beside the headline method, which takes a
+    # Jacobian and an LU on every step)
+    res["reuse"] = run("mixed", args.steps, args.warmup, jac_policy=1)
 
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
@@ -145,7 +149,7 @@ def headline(args):
                     mean_steps=float(r["stats"][:, 0].mean()),
                     max_steps=int(r["stats"][:, 0].max()))
 
-    sm, sf = summary(res["mixed"]), summary(res["fp64"])
+    sm, sf, sr = summary(res["mixed"]), summary(res["fp64"]), summary(res["reuse"])
 
     def roofline(s, precision):
         achieved = s["flops"] / (s["kernel_ms"] * 1e-3) / 1e12
@@ -174,15 +178,18 @@ def headline(args):
                "sample": f"{n} zones drawn uniformly (seed 12345) from the same 2^20-zone input, "
                          f"plain C FP64 oracle, OpenMP over zones, {ct:.1f} s wall"}
         accuracy = {}
-        for prec in ("mixed", "fp64"):
+        ref_r, ref_r_status, _ = oracle.burn(net_d, state0_np[idx], dt, rtol, atol, nthreads=threads,
+                                             jac_policy=1)
+        for prec in ("mixed", "fp64", "reuse"):
+            rs, rst = (ref_r, ref_r_status) if prec == "reuse" else (ref, ref_status)
             out = res[prec]["out"][idx][:, :nv]
-            ok = (ref_status == 0) & (res[prec]["status"][idx] == 0)
-            gated = np.abs(out[ok] - ref[ok, :nv]) / np.maximum(np.abs(ref[ok, :nv]), atol / rtol)
+            ok = (rst == 0) & (res[prec]["status"][idx] == 0)
+            gated = np.abs(out[ok] - rs[ok, :nv]) / np.maximum(np.abs(rs[ok, :nv]), atol / rtol)
             gz = gated.max(1)
             accuracy[prec] = {"max_gated_rel_err": float(gz.max()),
                               "zones_over_1e-6": int((gz > 1e-6).sum()),
                               "median_gated_rel_err": float(np.median(gz)),
-                              "status_mismatches": int((ref_status != res[prec]["status"][idx]).sum()),
+                              "status_mismatches": int((rst != res[prec]["status"][idx]).sum()),
                               "sampled_zones": n}
 
     line = {
@@ -206,6 +213,13 @@ def headline(args):
                        "kernel_ms": round(sf["kernel_ms"], 2), "roofline": roofline(sf, "fp64"),
                        "lanes_per_zone": sf["lanes_per_zone"]},
         "mixed_over_fp64": round(sm["value"] / sf["value"], 3),
+        "jac_reuse": {"value": round(sr["value"], 1), "ms_per_step": round(sr["ms_per_step"], 2),
+                      "kernel_ms": round(sr["kernel_ms"], 2), "precision": "mixed",
+                      "failed_zones": int((res["reuse"]["status"] != 0).sum()),
+                      "jacobians_per_zone": round(float(res["reuse"]["stats"][:, 2].mean()), 1),
+                      "lus_per_zone": round(float(res["reuse"]["stats"][:, 3].mean()), 1),
+                      "note": "VODE-style reuse of the Jacobian and LU (jac_policy 1); value counts "
+                              "OK zones; accuracy against the oracle's reuse policy"},
         "roofline": roofline(sm, "mixed"),
         "kernel_ms": round(sm["kernel_ms"], 2),
         "zone_steps": {"mean": round(sm["mean_steps"], 1), "max": sm["max_steps"]},

@@ -48,6 +48,12 @@ def lib():
         _lib.orc_burn_src.argtypes = [p, p, C.c_int64, p, p, d, d, d, i, p, p, i]
         _lib.orc_burn_retry.restype = i
         _lib.orc_burn_retry.argtypes = [p, p, C.c_int64, p, p, d, d, d, i, p, p, p, i]
+        _lib.orc_rkc.restype = i
+        _lib.orc_rkc.argtypes = [p, p, C.c_int64, p, p, d, d, d, i, p, p, i]
+        _lib.orc_rkc_fixed.restype = i
+        _lib.orc_rkc_fixed.argtypes = [p, p, p, d, i, i]
+        _lib.orc_rkc_stages.restype = i
+        _lib.orc_rkc_stages.argtypes = [d, d]
         _lib.orc_burn_ex.restype = i
         _lib.orc_burn_ex.argtypes = [p, p, C.c_int64, p, p, d, d, d, i, i, p, p, p, i]
         _lib.orc_burn_zone.restype = i
@@ -221,3 +227,33 @@ def radau(net, y0, dt, nsteps, h0=0.0, scale=None):
     if rc:
         raise RuntimeError(f"Radau Newton failed at step {-rc}")
     return y
+
+
+def rkc(net, state, dt, rtol, atol, scale=None, max_steps=100000, nthreads=None, source=None):
+    """Runge-Kutta-Chebyshev burn of a copy of state [zones][ns+1]; (state, status, stats)."""
+    n = _as_net(net)
+    st = np.array(state, dtype=np.float64, copy=True, order="C")
+    zones = st.shape[0]
+    if st.ndim != 2 or st.shape[1] != n.ns + 1:
+        raise ValueError("state must be [zones][ns+1]")
+    sc = None if scale is None else np.ascontiguousarray(scale, dtype=np.float64)
+    src = None if source is None else np.ascontiguousarray(source, dtype=np.float64)
+    status = np.zeros(zones, dtype=np.int32)
+    stats = np.zeros((zones, 7), dtype=np.int32)
+    lib().orc_rkc(n.ref, _dp(st), zones, _dp(sc), _dp(src), dt, rtol, atol, int(max_steps),
+                  _ip(status), _ip(stats), int(nthreads or os.cpu_count() or 1))
+    return st, status, stats
+
+
+def rkc_fixed(net, y, h, nsteps, s, scale=None):
+    """nsteps RKC steps of size h with s stages from y (one zone, [nv] values); returns y."""
+    n = _as_net(net)
+    v = np.array(y, dtype=np.float64, copy=True)
+    sc = None if scale is None else np.ascontiguousarray(scale, dtype=np.float64)
+    if lib().orc_rkc_fixed(n.ref, _dp(sc), _dp(v), float(h), int(nsteps), int(s)) != 0:
+        raise ValueError("bad stage count")
+    return v
+
+
+def rkc_stages(h, rho):
+    return int(lib().orc_rkc_stages(float(h), float(rho)))

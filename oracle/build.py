@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["net.c", "lu.c", "bdf.c", "radau.c"]
+SOURCES = ["net.c", "lu.c", "bdf.c", "radau.c", "rkc.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

@@ -82,6 +82,17 @@ int orc_fixed_steps(const orc_net *net, const double *scale, int q, double h, in
 /* Brute force: 2-stage Radau IIA on a geometric mesh (first step h0), full Newton. */
 int orc_radau(const orc_net *net, const double *scale, double *y, double dt, int64_t nsteps, double h0);
 
+/* Runge-Kutta-Chebyshev integrator (rkc.c): the damped second-order method for mildly stiff
+   zones, with the same state layout, statuses and counters as the BDF burn. */
+#define ORC_RKC_SMAX 250
+int orc_rkc_stages(double h, double rho);
+int orc_rkc_fixed(const orc_net *net, const double *scale, double *y, double h, int nsteps, int s);
+int orc_rkc_zone(const orc_net *net, double *row, const double *scale, const double *src, double dt,
+                 double rtol, double atol, int max_steps, orc_stats *st);
+int orc_rkc(const orc_net *net, double *state, int64_t zones, const double *scale, const double *source,
+            double dt, double rtol, double atol, int max_steps, int32_t *status, int32_t *stats,
+            int nthreads);
+
 /* Zone-by-zone retry of failed zones (the paper: retry an integration with different
    tolerances).  enabled = 0 turns it off. */
 typedef struct { int enabled; double rtol, atol; int max_steps; } orc_retry;

@@ -541,6 +541,64 @@ def test_reuse_robertson_and_benchmark_zones_match_scipy_radau():
         assert stats[0, 2] * 5 < stats[0, 0] and stats[0, 3] * 5 < stats[0, 0]
 
 
+# ------------------------------------------------- Runge-Kutta-Chebyshev (RKC)
+
+def _decay_network(lam):
+    """One species decaying into another: y0' = -lam y0."""
+    return W._net(2, 0, [[0, -1]], [[1, -1]], [math.log(lam)], [0.0], [0.0], [0.0])
+
+
+@pytest.mark.parametrize("s", [2, 3, 7, 20, 60])
+def test_rkc_step_is_the_damped_chebyshev_polynomial(s):
+    """On y' = lambda y one step of the damped RKC method multiplies y by
+    a_s + b_s T_s(w0 + w1 h lambda) (Sommeijer, Shampine & Verwer); the polynomial is taken
+    here from numpy's Chebyshev class, across the whole real stability interval."""
+    from numpy.polynomial import chebyshev as Ch
+    eps = 2.0 / 13.0
+    w0 = 1.0 + eps / s ** 2
+    Ts = Ch.Chebyshev.basis(s)
+    d1, d2 = Ts.deriv(1)(w0), Ts.deriv(2)(w0)
+    w1, bs = d1 / d2, d2 / d1 ** 2
+    a_s = 1.0 - bs * Ts(w0)
+    beta = (1.0 + w0) / w1                    # real stability interval: w0 + w1 z >= -1
+    for z in (-0.05, -1.0, -0.3 * beta, -0.95 * beta):
+        y = oracle.rkc_fixed(_decay_network(1.0), [1.0, 0.0], -z, 1, s)
+        R = a_s + bs * Ts(w0 + w1 * z)
+        assert abs(y[0] - R) < (1e-14 + 1e-15 * s * s) * max(1.0, abs(R)), (s, z)   # rounding of the recursion
+        assert abs(R) < 1.0                   # damped: stable inside the interval
+        assert abs(y[0] + y[1] - 1.0) < 1e-12 # the species sum is kept by every stage
+
+
+def test_rkc_is_second_order():
+    k, ya, yb, dt = 2.0, 0.6, 0.25, 0.5
+    net = W.two_body_network(k)
+    d = ya - yb
+    YB = d * yb / (ya * math.exp(k * d * dt) - yb)
+    errs = []
+    for n in (40, 80, 160):
+        y = oracle.rkc_fixed(net, [ya, yb, 0.05, 0.1], dt / n, n, 3)
+        errs.append(abs(y[1] - YB))
+    r = [errs[0] / errs[1], errs[1] / errs[2]]
+    assert all(3.5 < x < 4.5 for x in r), r
+
+
+def test_rkc_burn_matches_matrix_exponential_and_keeps_the_sum():
+    """A mildly stiff linear network (rates 1e-2 .. 1e2 per unit time) burned adaptively."""
+    ns = 6
+    net = W.linear_network(ns, 5, k_range=(1e-2, 1e2))
+    K = linear_K(net)
+    y0 = np.random.default_rng(5).dirichlet(np.ones(ns), size=4)
+    st = np.zeros((4, ns + 1))
+    st[:, :ns] = y0
+    out, status, stats = oracle.rkc(net, st, 10.0, 1e-6, 1e-10)
+    assert np.all(status == 0)
+    for z in range(4):
+        assert gated_err(out[z, :ns], sla.expm(K * 10.0) @ y0[z], rtol=1e-6, atol=1e-10) < 1e-4
+    assert np.abs(out[:, :ns].sum(1) - 1.0).max() < 1e-13
+    assert np.all(stats[:, 2] == stats[:, 0] + stats[:, 5])   # one Jacobian bound per attempt
+    assert np.all(stats[:, 1] > 2 * stats[:, 0])              # several stages per step
+
+
 # ------------------------------------------------------- zone-by-zone retry
 
 def test_retry_reruns_failed_zones_from_their_input():
