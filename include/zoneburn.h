@@ -77,6 +77,7 @@ typedef struct zb_server zb_server;
 enum { ZB_FP64 = 0, ZB_MIXED = 1 };               /* zb_opts.precision */
 enum { ZB_MAP_AUTO = 0 };                          /* zb_opts.mapping: else lanes per zone 1..64 */
 enum { ZB_JAC_EVERY_STEP = 0, ZB_JAC_REUSE = 1 };  /* zb_opts.jac_policy */
+enum { ZB_BDF = 0, ZB_RKC = 1 };                   /* zb_opts.integrator */
 
 typedef struct {
     int32_t max_steps;   /* accepted steps per zone before ZB_ZONE_MAXSTEPS (<= 0: 100000) */
@@ -102,6 +103,15 @@ typedef struct {
                             J unless the saved one is younger than 50 steps and gamma moved by
                             less than 20 %; a lagged matrix's correction is scaled by
                             2 / (1 + gamma / gamma_M).  The Jacobian stays in the zone's LDS. */
+    int32_t integrator;  /* ZB_BDF (0): the VODE-type BDF above.  ZB_RKC (1): the damped
+                            second-order Runge-Kutta-Chebyshev method the paper names beside VODE
+                            for mildly stiff zones (Sommeijer, Shampine & Verwer 1998; eps = 2/13,
+                            stages from the Gershgorin bound of the Jacobian, at most 250; error
+                            estimate (12 (y_n - y_{n+1}) + 6 h (F_n + F_{n+1})) / 15).  Same
+                            statuses, start, end clamp, abundance constraint and retry; counters
+                            nst, nfe, nje (one bound per attempt), netf.  FP64 only (no LU):
+                            ZB_EINVAL with ZB_MIXED.  jac_policy does not apply. */
+    int32_t reserved;
 } zb_opts;
 
 /* Create a context on HIP device `device` (allocates a small device workspace). */

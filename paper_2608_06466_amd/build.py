@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libzoneburn.so")
 # the burn-kernel instantiations are spread over several files so they compile in parallel
 SOURCES = ["zb_k48d.hip", "zb_k48f.hip", "zb_k48dr.hip", "zb_k48fr.hip", "zb_k16.hip",
            "zb_k16r.hip", "zb_k16n.hip", "zb_k24.hip", "zb_k24r.hip", "zb_k32.hip", "zb_k32r.hip",
-           "zb_k04.hip", "zb_k04r.hip", "zb_kernels.hip", "zb_host.hip", "zb_server.hip"]
+           "zb_k04.hip", "zb_k04r.hip", "zb_kc.hip", "zb_kernels.hip", "zb_host.hip", "zb_server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

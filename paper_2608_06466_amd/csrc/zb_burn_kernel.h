@@ -310,6 +310,10 @@ __device__ __forceinline__ bool gany(bool b)
     return greduce<L>(b ? 1 : 0, OpMax()) != 0;
 }
 
+// Integration methods (the compile-time third parameter of the burn kernel).
+enum { METHOD_BDF = 0, METHOD_BDF_REUSE = 1, METHOD_RKC = 2 };
+constexpr int RKC_SMAX = 250;
+
 // --------------------------------------------------------- BDF coefficients
 
 // l_j(q): coefficients of prod_{i<=q} (1 + x/i) divided by H_q (so l_1 = 1).
@@ -919,7 +923,7 @@ __device__ __forceinline__ int zone_start(const Ctx &c, Zone<NVP, L, LT> &z)
     z.q = 1;
     z.nequal = z.nefc = z.ncfc = 0;
 #pragma unroll
-    for (int s = 0; s < RPL; ++s) z.Z[1][s] = h * f0[s];
+    for (int s = 0; s < RPL; ++s) z.Z[1][s] = (c.jac_policy == METHOD_RKC) ? f0[s] : h * f0[s];
     return RUNNING;
 }
 
@@ -1185,6 +1189,139 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
     return RUNNING;
 }
 
+// One step attempt of the damped second-order Runge-Kutta-Chebyshev method
+// (Sommeijer, Shampine & Verwer; eps = 2/13), the integrator the paper names for
+// mildly stiff zones.  Z_0 holds y_n and Z_1 holds F(y_n).  The number of stages
+// comes from the Gershgorin bound of the Jacobian at y_n (assembled in LDS by the
+// network code), the stage coefficients from the Chebyshev three-term recurrences
+// (group-uniform scalars).  Error estimate (12 (y_n - y_{n+1}) + 6 h (F_n +
+// F_{n+1})) / 15, step factor min(10, max(0.1, 0.8 err^(-1/3))), and the start, end
+// clamp, abundance constraint and statuses of the BDF path.
+template <int NVP, int L, class LT>
+__device__ __forceinline__ int zone_attempt_rkc(const Ctx &c, Zone<NVP, L, LT> &z)
+{
+    constexpr int RPL = Zone<NVP, L, LT>::RPL;
+    constexpr int JS = NVP + 1;
+    const DevNet &N = c.net;
+    if (z.nst >= z.max_steps) return ZB_ZONE_MAXSTEPS;
+    bool last = false;
+    double h = z.h;
+    if (z.t + h >= c.dt * (1.0 - 4.0 * DBL_EPSILON)) {
+        h = c.dt - z.t;
+        last = true;
+    }
+    // spectral-radius bound: max over rows of sum_j |J_ij|
+    {
+        double tmp[RPL];
+        eval<true>(c, z, z.Z[0], tmp);
+        z.nje++;
+    }
+    lds_fence();
+    const double *jb = c.S + c.lay.jbuf;
+    double rs = 0.0;
+    sfor<0, RPL>([&](auto S) {
+        const int i = row_of<NVP, L>(c, S);
+        if (i < N.nv) {
+            double r = 0.0;
+            for (int j = 0; j < N.nv; ++j) r += fabs(jb[i * JS + j]);
+            rs = fmax(rs, r);
+        }
+    });
+    const double rho = greduce<L>(rs, OpMax());
+    const double hstab = ((double)(RKC_SMAX - 1) * (RKC_SMAX - 1) - 1.0) / (1.54 * rho);
+    if (h > hstab) {
+        h = hstab;
+        last = false;
+    }
+    int ns = 1 + (int)floor(sqrt(1.0 + 1.54 * h * rho));
+    ns = ns < 2 ? 2 : ns;
+    // w1 = T_s'(w0) / T_s''(w0)
+    const double w0 = 1.0 + (2.0 / 13.0) / ((double)ns * ns);
+    double w1;
+    {
+        double t0 = 1.0, t1 = w0, d0 = 0.0, d1 = 1.0, e0 = 0.0, e1 = 0.0;
+        for (int j = 2; j <= ns; ++j) {
+            const double t2 = 2.0 * w0 * t1 - t0;
+            const double d2 = 2.0 * t1 + 2.0 * w0 * d1 - d0;
+            const double e2 = 4.0 * d1 + 2.0 * w0 * e1 - e0;
+            t0 = t1; t1 = t2; d0 = d1; d1 = d2; e0 = e1; e1 = e2;
+        }
+        w1 = d1 / e1;
+    }
+    // stages; running T_j, T_j', T_j'' and b_j (b_0 = b_1 = b_2)
+    double Y2[RPL], Y1[RPL], F[RPL];
+    double T1 = w0, Tm = 1.0, D1 = 1.0, Dm = 0.0, E1 = 0.0, Em = 0.0;   // j-1 and j-2 values
+    double T2 = 2.0 * w0 * T1 - Tm, D2 = 2.0 * T1 + 2.0 * w0 * D1 - Dm, E2 = 4.0 * D1 + 2.0 * w0 * E1 - Em;
+    const double b2 = E2 / (D2 * D2);
+    double bjm1 = b2, bjm2 = b2;   // b_1, b_0
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        Y2[s] = z.Z[0][s];
+        Y1[s] = z.Z[0][s] + bjm1 * w1 * h * z.Z[1][s];
+    }
+    double Tjm1 = T1;              // T_{j-1}(w0) for j = 2
+    double Tc = T1, Tp = Tm, Dc = D1, Dp = Dm, Ec = E1, Ep = Em;
+    for (int j = 2; j <= ns; ++j) {
+        const double Tn = 2.0 * w0 * Tc - Tp, Dn = 2.0 * Tc + 2.0 * w0 * Dc - Dp, En = 4.0 * Dc + 2.0 * w0 * Ec - Ep;
+        const double bj = (j == 2) ? b2 : En / (Dn * Dn);
+        const double mu = 2.0 * bj * w0 / bjm1;
+        const double nu = -bj / bjm2;
+        const double mut = 2.0 * bj * w1 / bjm1;
+        const double gat = -(1.0 - bjm1 * Tjm1) * mut;
+        eval<false>(c, z, Y1, F);
+        z.nfe++;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) {
+            const double yj = (1.0 - mu - nu) * z.Z[0][s] + mu * Y1[s] + nu * Y2[s] + mut * h * F[s] + gat * h * z.Z[1][s];
+            Y2[s] = Y1[s];
+            Y1[s] = yj;
+        }
+        Tp = Tc; Tc = Tn; Dp = Dc; Dc = Dn; Ep = Ec; Ec = En;
+        Tjm1 = Tn;
+        bjm2 = bjm1;
+        bjm1 = bj;
+    }
+    // error estimate at y_{n+1} = Y1
+    eval<false>(c, z, Y1, F);
+    z.nfe++;
+    double se = 0.0, feas = 1.0;
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        const int i = row_of<NVP, L>(c, s);
+        if (i < N.nv) {
+            const double est = (12.0 * (z.Z[0][s] - Y1[s]) + 6.0 * h * (z.Z[1][s] + F[s])) / 15.0;
+            const double w = z.atol + z.rtol * fmax(fabs(z.Z[0][s]), fabs(Y1[s]));
+            const double x = est / w;
+            se = fma(x, x, se);
+            if (i < N.ns && Y1[s] < -z.atol)
+                feas = fmin(feas, (z.Z[0][s] + z.atol) / (z.Z[0][s] - Y1[s]));
+        }
+    }
+    double err = sqrt(greduce<L>(se, OpAdd()) / (double)N.nv);
+    feas = greduce<L>(feas, OpMin());
+    if (!isfinite(err)) err = 1e10;
+    double fac = fmin(10.0, fmax(0.1, 0.8 * pow(err, -1.0 / 3.0)));
+    if (err > 1.0 || feas < 1.0) {
+        z.netf++;
+        if (++z.nefc >= 10) return ZB_ZONE_ERRTEST;
+        if (feas < 1.0) fac = fmin(fac, fmax(0.1, 0.9 * feas));
+        z.h = h * fmin(fac, 1.0);
+        if (z.t + z.h == z.t) return ZB_ZONE_HMIN;
+        return RUNNING;
+    }
+    z.nefc = 0;
+#pragma unroll
+    for (int s = 0; s < RPL; ++s) {
+        z.Z[0][s] = Y1[s];
+        z.Z[1][s] = F[s];
+    }
+    z.t = last ? c.dt : z.t + h;
+    z.nst++;
+    if (last) return ZB_ZONE_OK;
+    z.h = h * fac;
+    return RUNNING;
+}
+
 template <int NVP, int L, class LT>
 __device__ __forceinline__ void zone_finish(const Ctx &c, Zone<NVP, L, LT> &z, int status, const BurnArgs &A)
 {
@@ -1328,7 +1465,7 @@ void burn_kernel(BurnArgs A)
             continue;
         }
         if (!need) {
-            int st = zone_attempt(c, z);
+            int st = (JP == METHOD_RKC) ? zone_attempt_rkc(c, z) : zone_attempt(c, z);
             if (st != RUNNING) {
                 if (st != ZB_ZONE_OK && A.retry && z.tries == 0) {
                     // Zone-by-zone retry with the retry tolerances, from the zone's input
@@ -1357,5 +1494,6 @@ void burn_kernel(BurnArgs A)
 
 #define ZB_K(NVP, L, LT, MIX) {NVP, L, MIX, 0, (const void *)&burn_kernel<NVP, L, LT, 0>}
 #define ZB_KR(NVP, L, LT, MIX) {NVP, L, MIX, 1, (const void *)&burn_kernel<NVP, L, LT, 1>}
+#define ZB_KC(NVP, L) {NVP, L, 0, 2, (const void *)&burn_kernel<NVP, L, double, 2>}
 
 }  // namespace zb

@@ -387,7 +387,11 @@ static zb_err plan_groups(zb_context *ctx, const zb_segment *segs, int n, const 
         return fail(ZB_EINVAL, "retry needs finite retry_rtol > 0 and retry_atol > 0");
     if (opts && opts->jac_policy != ZB_JAC_EVERY_STEP && opts->jac_policy != ZB_JAC_REUSE)
         return fail(ZB_EINVAL, "jac_policy %d", opts->jac_policy);
-    const int jac = opts ? opts->jac_policy : 0;
+    if (opts && opts->integrator != ZB_BDF && opts->integrator != ZB_RKC)
+        return fail(ZB_EINVAL, "integrator %d", opts->integrator);
+    const bool rkc = opts && opts->integrator == ZB_RKC;
+    if (rkc && prec == ZB_MIXED) return fail(ZB_EINVAL, "the RKC integrator has no LU: use ZB_FP64");
+    const int jac = rkc ? 2 : (opts ? opts->jac_policy : 0);
     for (int i = 0; i < n; ++i) {
         zb_err e = check_segment(ctx, segs[i]);
         if (e != ZB_OK) return e;

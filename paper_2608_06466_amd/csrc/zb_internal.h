@@ -84,7 +84,7 @@ struct KernelInfo {
     int nvp;          // padded number of variables the kernel handles (nv <= nvp)
     int lanes;        // lanes per zone
     int mixed;        // 0: FP64 LU, 1: FP32 LU
-    int jac;          // jac_policy the kernel implements (0 every step, 1 reuse)
+    int jac;          // method: 0 BDF with J every step, 1 BDF with reuse, 2 RKC
     const void *fn;   // __global__ function
 };
 

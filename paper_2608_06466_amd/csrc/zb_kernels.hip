@@ -20,6 +20,7 @@ int kernels_24r(const KernelInfo **out);
 int kernels_32r(const KernelInfo **out);
 int kernels_48dr(const KernelInfo **out);
 int kernels_48fr(const KernelInfo **out);
+int kernels_rkc(const KernelInfo **out);
 
 __global__ void reset_kernel(unsigned long long *p, int n)
 {
@@ -55,6 +56,7 @@ int kernel_table(const KernelInfo **out)
         add(kernels_32r);
         add(kernels_48dr);
         add(kernels_48fr);
+        add(kernels_rkc);
         return t;
     }();
     *out = table.data();

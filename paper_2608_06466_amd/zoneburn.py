@@ -39,7 +39,8 @@ class _Desc(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("max_steps", C.c_int32), ("precision", C.c_int32), ("mapping", C.c_int32),
                 ("retry", C.c_int32), ("retry_rtol", C.c_double), ("retry_atol", C.c_double),
-                ("retry_max_steps", C.c_int32), ("jac_policy", C.c_int32)]
+                ("retry_max_steps", C.c_int32), ("jac_policy", C.c_int32),
+                ("integrator", C.c_int32), ("reserved", C.c_int32)]
 
 
 class _Segment(C.Structure):
@@ -180,15 +181,20 @@ class Network:
 JAC_EVERY_STEP, JAC_REUSE = 0, 1
 
 
-def _opts(precision, lanes, max_steps, retry=None, jac_policy=0):
+BDF, RKC = 0, 1
+
+
+def _opts(precision, lanes, max_steps, retry=None, jac_policy=0, integrator=0):
     """retry: None, or (rtol, atol, max_steps) of the zone-by-zone retry of failed zones.
-    jac_policy: 0 Jacobian and LU every step attempt, 1 VODE-style reuse."""
+    jac_policy: 0 Jacobian and LU every step attempt, 1 VODE-style reuse.
+    integrator: "bdf" (0) or "rkc" (1)."""
     prec = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}[precision]
     jp = {"every_step": 0, "reuse": 1, 0: 0, 1: 1}[jac_policy]
+    it = {"bdf": 0, "rkc": 1, 0: 0, 1: 1}[integrator]
     if retry is None:
-        return _Opts(int(max_steps or 0), prec, int(lanes or 0), 0, 0.0, 0.0, 0, jp)
+        return _Opts(int(max_steps or 0), prec, int(lanes or 0), 0, 0.0, 0.0, 0, jp, it, 0)
     return _Opts(int(max_steps or 0), prec, int(lanes or 0), 1, float(retry[0]), float(retry[1]),
-                 int(retry[2]), jp)
+                 int(retry[2]), jp, it, 0)
 
 
 def _check_state(net, state):
@@ -200,7 +206,7 @@ def _check_state(net, state):
 
 def burn(ctx, net, state, dt, rtol, atol, rate_scale=None, precision="fp64", lanes=0,
          max_steps=0, want_status=True, want_stats=True, stream=None, source=None, retry=None,
-         jac_policy=0):
+         jac_policy=0, integrator="bdf"):
     """In-place burn of state [zones][ns+1]; returns (status int32[zones], stats int32[zones,7]).
 
     source: optional constant per-zone term [zones][ns+1] added to the right-hand side
@@ -214,7 +220,7 @@ def burn(ctx, net, state, dt, rtol, atol, rate_scale=None, precision="fp64", lan
         burn_batch(ctx, [dict(net=net, state=state, dt=dt, rtol=rtol, atol=atol, rate_scale=rate_scale,
                               status=status, stats=stats, source=source)],
                    precision=precision, lanes=lanes, max_steps=max_steps, stream=stream, retry=retry,
-                   jac_policy=jac_policy)
+                   jac_policy=jac_policy, integrator=integrator)
         return status, stats
     zones = state.shape[0]
     if rate_scale is not None and (rate_scale.dtype != torch.float64 or not rate_scale.is_cuda
@@ -223,7 +229,7 @@ def burn(ctx, net, state, dt, rtol, atol, rate_scale=None, precision="fp64", lan
         raise ValueError("rate_scale must be a contiguous float64 CUDA tensor [zones][R]")
     status = torch.empty(zones, dtype=torch.int32, device=state.device) if want_status else None
     stats = torch.empty((zones, 7), dtype=torch.int32, device=state.device) if want_stats else None
-    o = _opts(precision, lanes, max_steps, retry, jac_policy)
+    o = _opts(precision, lanes, max_steps, retry, jac_policy, integrator)
     _check(lib().zb_burn(ctx.h, net.h, _ptr(state), zones, float(dt), float(rtol), float(atol),
                          _ptr(rate_scale), C.byref(o), _ptr(status), _ptr(stats),
                          _stream_handle(stream)), "zb_burn")
@@ -254,11 +260,11 @@ def _segments(segments):
 
 
 def burn_batch(ctx, segments, precision="fp64", lanes=0, max_steps=0, stream=None, retry=None,
-               jac_policy=0):
+               jac_policy=0, integrator="bdf"):
     """segments: list of dicts(net, state, dt, rtol, atol, rate_scale=None, status=None,
     stats=None, source=None); retry: None or (rtol, atol, max_steps)."""
     arr = _segments(segments)
-    o = _opts(precision, lanes, max_steps, retry, jac_policy)
+    o = _opts(precision, lanes, max_steps, retry, jac_policy, integrator)
     _check(lib().zb_burn_batch(ctx.h, arr, len(segments), C.byref(o), _stream_handle(stream)),
            "zb_burn_batch")
 

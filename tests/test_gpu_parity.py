@@ -441,3 +441,49 @@ def test_jacobian_reuse_parity(zbm, which, precision):
     for s in (out[0][2][ok], ref[2][ok]):
         assert s[:, 2].sum() * 4 < s[:, 0].sum() and s[:, 3].sum() * 3 < s[:, 0].sum()
     net.close()
+
+
+@pytest.mark.parametrize("which", ["nv14", "nv22", "nv48", "linear"])
+def test_rkc_parity(zbm, which):
+    """The Runge-Kutta-Chebyshev integrator against the oracle's, on mildly stiff zones (the
+    random networks at 100-300 K; a linear network with rates 1e-2..1e2): same statuses and
+    results within the widened bar (each side's own error from a run at rtol/100)."""
+    zb, ctx = zbm
+    rtol, atol, dt = 1e-6, 1e-10, 1.0
+    if which == "linear":
+        net_d = W.linear_network(6, 5, k_range=(1e-2, 1e2))
+        st = np.zeros((128, 7))
+        st[:, :6] = np.random.default_rng(3).dirichlet(np.ones(6), size=128)
+        dt = 10.0
+    else:
+        k = {"nv14": 0, "nv22": 1, "nv48": 2}[which]
+        ns, R, seed = W.CONFIG3_NETS[k]
+        net_d = W.random_network(ns, R, seed)
+        st = W.random_zones(net_d, [256, 128, 48][k], seed=31, T_range=(100.0, 300.0), T_dist="loguniform")
+    ref = oracle.rkc(net_d, st, dt, rtol, atol)
+    fine = oracle.rkc(net_d, st, dt, rtol / 100, atol / 100, max_steps=10000000)
+    net = zb.Network(ctx, net_d)
+    out = []
+    for rt, at in ((rtol, atol), (rtol / 100, atol / 100)):
+        t = torch.tensor(st, device="cuda:0")
+        status, stats = zb.burn(ctx, net, t, dt, rt, at, integrator="rkc", max_steps=10000000)
+        zb.sync(ctx)
+        out.append((t.cpu().numpy(), status.cpu().numpy(), stats.cpu().numpy()))
+    nv = net_d["n_species"] + net_d["thermal"]
+    assert np.all(ref[1] == 0)
+    check(f"rkc {which}", out[0], (ref, fine), rtol, atol, nv, out[1])
+    # one Jacobian bound per attempt, several stages per step, no LU on either side
+    for s in (out[0][2], ref[2]):
+        assert np.all(s[:, 2] == s[:, 0] + s[:, 5]) and np.all(s[:, 3] == 0)
+    net.close()
+
+
+def test_rkc_rejects_mixed_precision(zbm):
+    zb, ctx = zbm
+    c = W.config2(4)
+    net = zb.Network(ctx, c["net"])
+    with pytest.raises(zb.ZoneburnError) as e:
+        zb.burn(ctx, net, torch.tensor(c["state"], device="cuda:0"), 1.0, 1e-6, 1e-10,
+                precision="mixed", integrator="rkc")
+    assert e.value.code == zb.EINVAL
+    net.close()
