@@ -61,6 +61,7 @@ def lib():
         _lib.orc_rhs.argtypes = [p, p, p, p]
         _lib.orc_rhs_cplx.argtypes = [p, p, p, p]
         _lib.orc_jac.argtypes = [p, p, p, p]
+        _lib.orc_fd_jac.argtypes = [p, p, p, p, d, d, p]
         _lib.orc_rates.argtypes = [p, p, p, p, p]
         _lib.orc_lu.restype = i
         _lib.orc_lu.argtypes = [i, p, p]
@@ -108,7 +109,7 @@ def _as_net(net):
 
 class _Retry(C.Structure):
     _fields_ = [("enabled", C.c_int), ("rtol", C.c_double), ("atol", C.c_double),
-                ("max_steps", C.c_int)]
+                ("max_steps", C.c_int), ("jac", C.c_int)]
 
 
 def burn(net, state, dt, rtol, atol, scale=None, max_steps=100000, nthreads=None, source=None,
@@ -116,8 +117,9 @@ def burn(net, state, dt, rtol, atol, scale=None, max_steps=100000, nthreads=None
     """Burn a copy of state [zones][ns+1]; returns (state, status[zones], stats[zones,7]).
 
     source: optional constant per-zone term [zones][ns+1] added to the right-hand side.
-    retry: optional (rtol, atol, max_steps) for a second run of every failed zone from its
-    input; such a zone then reports status 6 when the retry succeeds.
+    retry: optional (rtol, atol, max_steps[, jac]) for a second run of every failed zone
+    from its input, jac "analytic" (default) or "fd" (finite-difference Jacobian); such a
+    zone then reports status 6 when the retry succeeds.
     jac_policy: 0 Jacobian and LU every step attempt, 1 VODE-style reuse."""
     n = _as_net(net)
     st = np.array(state, dtype=np.float64, copy=True, order="C")
@@ -134,7 +136,12 @@ def burn(net, state, dt, rtol, atol, scale=None, max_steps=100000, nthreads=None
     src = None if source is None else np.ascontiguousarray(source, dtype=np.float64)
     if src is not None and src.shape != st.shape:
         raise ValueError("source must be [zones][ns+1]")
-    rt = None if retry is None else _Retry(1, float(retry[0]), float(retry[1]), int(retry[2]))
+    rt = None
+    if retry is not None:
+        rjac = retry[3] if len(retry) > 3 else "analytic"
+        if rjac not in ("analytic", "fd"):
+            raise ValueError("retry jac must be 'analytic' or 'fd'")
+        rt = _Retry(1, float(retry[0]), float(retry[1]), int(retry[2]), int(rjac == "fd"))
     lib().orc_burn_ex(n.ref, _dp(st), zones, _dp(sc), _dp(src), dt, rtol, atol, int(max_steps),
                       int(jac_policy), None if rt is None else C.byref(rt), _ip(status), _ip(stats),
                       int(nthreads))
@@ -165,6 +172,17 @@ def jac(net, y, scale=None):
     J = np.zeros((n.nv, n.nv))
     sc = None if scale is None else np.ascontiguousarray(scale, dtype=np.float64)
     lib().orc_jac(n.ref, _dp(sc), _dp(y), _dp(J))
+    return J
+
+
+def fd_jac(net, y, rtol, atol, scale=None, source=None):
+    """Finite-difference Jacobian of the RHS (plus source) at y (the retry's alternative)."""
+    n = _as_net(net)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    J = np.zeros((n.nv, n.nv))
+    sc = None if scale is None else np.ascontiguousarray(scale, dtype=np.float64)
+    src = None if source is None else np.ascontiguousarray(source, dtype=np.float64)
+    lib().orc_fd_jac(n.ref, _dp(sc), _dp(src), _dp(y), float(rtol), float(atol), _dp(J))
     return J
 
 

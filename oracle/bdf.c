@@ -148,6 +148,8 @@ static void predict(int nv, int q, double *Z)
    2 / (1 + gamma / gamma_M), the factor VODE applies to a lagged matrix. */
 typedef struct {
     int policy;
+    int fd;                      /* 1: finite-difference Jacobian (a retry's alternative) */
+    double rtol, atol;           /* the run's tolerances (they scale the differences) */
     int have_j, have_m;
     int nst_j, nst_m;            /* nst when J was evaluated / M was factored */
     double gamma_m;
@@ -168,9 +170,43 @@ static void form_lu(const sys_t *S, jac_t *J, double gamma, orc_stats *st)
     J->nst_m = st->nst;
 }
 
+/* Finite-difference Jacobian: the other Jacobian approximation the paper names for a
+   zone-by-zone retry (Software design).  Forward differences in each variable with the
+   step d_j = 2^-26 max(|y_j|, atol + rtol |y_j|) (the square root of the FP64 unit
+   roundoff times the variable's scale), replaced by (y_j + d_j) - y_j so that it is
+   exactly the change applied.  The nv perturbed evaluations count as RHS evaluations;
+   f(y) itself is the RHS at the prediction, which Newton counts. */
+static void fd_jac(const sys_t *S, const double *y, double rtol, double atol, double *Jm,
+                   orc_stats *st)
+{
+    int nv = S->nv;
+    double f0[ORC_NVMAX], f1[ORC_NVMAX], yp[ORC_NVMAX];
+    orc_stats uncounted;
+    rhs(S, y, f0, &uncounted);
+    for (int j = 0; j < nv; j++) {
+        for (int i = 0; i < nv; i++) yp[i] = y[i];
+        double d = ldexp(1.0, -26) * fmax(fabs(y[j]), atol + rtol * fabs(y[j]));
+        yp[j] = y[j] + d;
+        d = yp[j] - y[j];
+        rhs(S, yp, f1, st);
+        for (int i = 0; i < nv; i++) Jm[i * nv + j] = (f1[i] - f0[i]) / d;
+    }
+}
+
+void orc_fd_jac(const orc_net *net, const double *scale, const double *src, const double *y,
+                double rtol, double atol, double *J)
+{
+    sys_t S = {net, scale, orc_nvar(net), src};
+    orc_stats st;
+    fd_jac(&S, y, rtol, atol, J, &st);
+}
+
 static void eval_jac(const sys_t *S, jac_t *J, const double *y, orc_stats *st)
 {
-    orc_jac(S->net, S->scale, y, J->J);
+    if (J->fd)
+        fd_jac(S, y, J->rtol, J->atol, J->J, st);
+    else
+        orc_jac(S->net, S->scale, y, J->J);
     st->nje++;
     J->have_j = 1;
     J->nst_j = st->nst;
@@ -257,23 +293,26 @@ static void correct(int nv, int q, double *Z, const double *y, const double *dy)
 int orc_burn_zone(const orc_net *net, double *row, const double *scale, double dt, double rtol,
                   double atol, int max_steps, orc_stats *st)
 {
-    return orc_burn_zone_ex(net, row, scale, NULL, dt, rtol, atol, max_steps, 0, st);
+    return orc_burn_zone_ex(net, row, scale, NULL, dt, rtol, atol, max_steps, 0, 0, st);
 }
 
 int orc_burn_zone_src(const orc_net *net, double *row, const double *scale, const double *src,
                       double dt, double rtol, double atol, int max_steps, orc_stats *st)
 {
-    return orc_burn_zone_ex(net, row, scale, src, dt, rtol, atol, max_steps, 0, st);
+    return orc_burn_zone_ex(net, row, scale, src, dt, rtol, atol, max_steps, 0, 0, st);
 }
 
 int orc_burn_zone_ex(const orc_net *net, double *row, const double *scale, const double *src,
                      double dt, double rtol, double atol, int max_steps, int jac_policy,
-                     orc_stats *st)
+                     int fd_jac, orc_stats *st)
 {
     sys_t S = {net, scale, orc_nvar(net), src};
     jac_t J;
     memset(&J, 0, sizeof J);
     J.policy = jac_policy;
+    J.fd = fd_jac;
+    J.rtol = rtol;
+    J.atol = atol;
     int nv = S.nv;
     double Z[(ORC_QMAX + 2) * ORC_NVMAX], Zs[(ORC_QMAX + 2) * ORC_NVMAX];
     double w[ORC_NVMAX], f0[ORC_NVMAX], f1[ORC_NVMAX], y1[ORC_NVMAX];
@@ -446,7 +485,8 @@ int orc_burn_src(const orc_net *net, double *state, int64_t zones, const double 
 }
 
 /* A failed zone (any status but ORC_OK) is integrated once more from its input with the
-   retry tolerances and step cap (the paper's zone-by-zone retry); success then reports
+   retry tolerances, step cap and Jacobian (analytic, or finite differences) (the paper's
+   zone-by-zone retry); success then reports
    ORC_OK_RETRY, a second failure that run's status.  Counters add up over both runs. */
 int orc_burn_retry(const orc_net *net, double *state, int64_t zones, const double *scale,
                    const double *source, double dt, double rtol, double atol, int max_steps,
@@ -471,12 +511,12 @@ int orc_burn_ex(const orc_net *net, double *state, int64_t zones, const double *
         const double *sc = scale ? scale + z * net->nr : NULL;
         const double *sr = source ? source + z * row : NULL;
         memcpy(in, y, sizeof(double) * row);
-        int s = orc_burn_zone_ex(net, y, sc, sr, dt, rtol, atol, max_steps, jac_policy, &st);
+        int s = orc_burn_zone_ex(net, y, sc, sr, dt, rtol, atol, max_steps, jac_policy, 0, &st);
         if (s != ORC_OK && retry && retry->enabled) {
             orc_stats st2;
             memcpy(y, in, sizeof(double) * row);
             s = orc_burn_zone_ex(net, y, sc, sr, dt, retry->rtol, retry->atol, retry->max_steps,
-                                 jac_policy, &st2);
+                                 jac_policy, retry->jac, &st2);
             if (s == ORC_OK) s = ORC_OK_RETRY;
             st.nst += st2.nst; st.nfe += st2.nfe; st.nje += st2.nje; st.nlu += st2.nlu;
             st.nni += st2.nni; st.netf += st2.netf; st.ncf += st2.ncf;

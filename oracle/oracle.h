@@ -95,7 +95,9 @@ int orc_rkc(const orc_net *net, double *state, int64_t zones, const double *scal
 
 /* Zone-by-zone retry of failed zones (the paper: retry an integration with different
    tolerances).  enabled = 0 turns it off. */
-typedef struct { int enabled; double rtol, atol; int max_steps; } orc_retry;
+/* jac: the retry's Jacobian, 0 analytic (as in the first run), 1 finite differences
+   (orc_fd_jac). */
+typedef struct { int enabled; double rtol, atol; int max_steps; int jac; } orc_retry;
 int orc_burn_retry(const orc_net *net, double *state, int64_t zones, const double *scale,
                    const double *source, double dt, double rtol, double atol, int max_steps,
                    const orc_retry *retry, int32_t *status, int32_t *stats, int nthreads);
@@ -104,7 +106,12 @@ int orc_burn_retry(const orc_net *net, double *state, int64_t zones, const doubl
    jac_policy 1: VODE-style reuse of the iteration matrix and the Jacobian (rules in bdf.c). */
 int orc_burn_zone_ex(const orc_net *net, double *row, const double *scale, const double *src,
                      double dt, double rtol, double atol, int max_steps, int jac_policy,
-                     orc_stats *st);
+                     int fd_jac, orc_stats *st);
+/* Finite-difference Jacobian of f (the network RHS plus src, if any) at y, row-major
+   [nv][nv]: column j is (f(y + d_j e_j) - f(y)) / d_j with d_j = 2^-26 max(|y_j|,
+   atol + rtol |y_j|), taken as (y_j + d_j) - y_j. */
+void orc_fd_jac(const orc_net *net, const double *scale, const double *src, const double *y,
+                double rtol, double atol, double *J);
 int orc_burn_ex(const orc_net *net, double *state, int64_t zones, const double *scale,
                 const double *source, double dt, double rtol, double atol, int max_steps,
                 int jac_policy, const orc_retry *retry, int32_t *status, int32_t *stats,

@@ -103,14 +103,18 @@ static void rkc_step(const orc_net *net, const double *scale, const double *src,
     T[0] = 1.0; T[1] = w0;
     dT[0] = 0.0; dT[1] = 1.0;
     ddT[0] = 0.0; ddT[1] = 0.0;
-    for (int j = 2; j <= s; j++) {
+    /* s >= 2: the j = 2 terms always exist */
+    T[2] = 2.0 * w0 * T[1] - T[0];
+    dT[2] = 2.0 * T[1] + 2.0 * w0 * dT[1] - dT[0];
+    ddT[2] = 4.0 * dT[1] + 2.0 * w0 * ddT[1] - ddT[0];
+    for (int j = 3; j <= s; j++) {
         T[j] = 2.0 * w0 * T[j - 1] - T[j - 2];
         dT[j] = 2.0 * T[j - 1] + 2.0 * w0 * dT[j - 1] - dT[j - 2];
         ddT[j] = 4.0 * dT[j - 1] + 2.0 * w0 * ddT[j - 1] - ddT[j - 2];
     }
     const double w1 = dT[s] / ddT[s];
     double b[ORC_RKC_SMAX + 1];
-    b[2] = ddT[2] / (dT[2] * dT[2]);   /* s >= 2 */
+    b[2] = ddT[2] / (dT[2] * dT[2]);
     for (int j = 3; j <= s; j++) b[j] = ddT[j] / (dT[j] * dT[j]);
     b[0] = b[1] = b[2];
 

@@ -628,6 +628,88 @@ def test_retry_that_fails_again_reports_the_retry_status():
     assert np.all(rt[2][:, 0] == 110)           # 50 + 60 accepted steps
 
 
+# ------------------------------------- finite-difference Jacobian (a retry's alternative)
+
+@pytest.mark.parametrize("name,net,y", list(_nets()), ids=[n for n, _, _ in _nets()])
+def test_fd_jacobian_approximates_the_analytic_one(name, net, y):
+    """Forward differences with steps of 2^-26 times the variable's scale agree with the
+    analytic Jacobian (itself pinned to the complex-step derivative) to first order in the
+    step, column by column; species that react nowhere give exactly zero columns."""
+    n = oracle.Net(net)
+    y = np.asarray(y, dtype=float)[: n.nv]
+    J = oracle.jac(n, y)
+    Jf = oracle.fd_jac(n, y, RTOL, ATOL)
+    f = oracle.rhs(n, y)
+    for j in range(n.nv):
+        d = 2.0 ** -26 * max(abs(y[j]), ATOL + RTOL * abs(y[j]))
+        col = np.abs(J[:, j]).max()
+        # truncation ~ d |f''| (bounded through the column scale) + rounding ~ eps |f| / d
+        bound = 1e-6 * col + 8 * np.finfo(float).eps * np.abs(f).max() / d
+        assert np.abs(Jf[:, j] - J[:, j]).max() <= bound, (name, j)
+        if col == 0.0:
+            assert np.all(Jf[:, j] == 0.0)
+
+
+def test_fd_jacobian_of_a_linear_network_is_its_matrix():
+    net = W.linear_network(6, 4)
+    K = linear_K(net)
+    y = np.random.default_rng(3).dirichlet(np.ones(6))
+    y = np.append(y, 0.0)[: oracle.Net(net).nv]
+    Jf = oracle.fd_jac(net, y, RTOL, ATOL)
+    # f is linear, so only rounding separates the differences from K: ~eps |f| / d_j
+    fmax = np.abs(oracle.rhs(net, y)).max()
+    d = 2.0 ** -26 * np.maximum(np.abs(y[:6]), ATOL + RTOL * np.abs(y[:6]))
+    bound = 1e-12 * np.abs(K).max(axis=0) + 8 * np.finfo(float).eps * fmax / d
+    assert np.all(np.abs(Jf[:6, :6] - K) <= bound[None, :])
+    # a constant source changes f, not its differences
+    src = np.linspace(0.1, 0.7, Jf.shape[0])
+    fmax_s = np.abs(oracle.rhs(net, y) + src).max()
+    bound_s = 2 * bound + 8 * np.finfo(float).eps * fmax_s / d
+    Js = oracle.fd_jac(net, y, RTOL, ATOL, source=src)
+    assert np.all(np.abs(Js[:6, :6] - K) <= bound_s[None, :])
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_fd_retry_linear_network_matches_matrix_exponential(seed):
+    """A first run capped at 3 steps fails; the retry with the finite-difference Jacobian
+    reaches the exact solution.  Counting: with a Jacobian on every attempt the integrator's
+    own RHS evaluations are 2 at the start plus one per Newton iteration, and each
+    finite-difference Jacobian adds nv."""
+    ns = 4 + seed
+    net = W.linear_network(ns, seed)
+    K = linear_K(net)
+    y0 = np.random.default_rng(seed).dirichlet(np.ones(ns))
+    st = np.zeros((1, ns + 1))
+    st[0, :ns] = y0
+    fd = oracle.burn(net, st, 10.0, RTOL, ATOL, max_steps=3, retry=(RTOL, ATOL, 100000, "fd"))
+    an = oracle.burn(net, st, 10.0, RTOL, ATOL, max_steps=3, retry=(RTOL, ATOL, 100000))
+    assert fd[1][0] == 6 and an[1][0] == 6
+    assert gated_err(fd[0][0, :ns], sla.expm(K * 10.0) @ y0) < 1e-6
+    first = oracle.burn(net, st, 10.0, RTOL, ATOL, max_steps=3)[2][0]
+    a2, f2 = an[2][0] - first, fd[2][0] - first         # the retry passes alone
+    nv = oracle.Net(net).nv
+    assert a2[1] == 2 + a2[4]                           # nfe = 2 + nni
+    assert f2[1] == 2 + f2[4] + nv * f2[2]              # + nv per Jacobian
+    assert f2[2] == f2[3] and abs(int(f2[0]) - int(a2[0])) <= 2
+
+
+def test_fd_retry_on_the_benchmark_network():
+    """Zones that fail a 1500-step cap, retried with finite differences at loose tolerances,
+    succeed and meet those tolerances against a tight reference."""
+    c = W.config2(48)
+    rt = oracle.burn(c["net"], c["state"], 1.0, RTOL, ATOL, max_steps=1500,
+                     retry=(1e-6, 1e-10, 100000, "fd"))
+    plain = oracle.burn(c["net"], c["state"], 1.0, RTOL, ATOL, max_steps=1500)
+    failed = plain[1] != 0
+    assert failed.sum() > 5
+    assert np.all(rt[1][failed] == 6) and np.all(rt[1][~failed] == 0)
+    assert np.array_equal(rt[0][~failed], plain[0][~failed])
+    fine = oracle.burn(c["net"], c["state"][failed], 1.0, 1e-11, 1e-15)
+    assert gated_err(rt[0][failed][:, :14], fine[0][:, :14], rtol=1e-6, atol=1e-10) < 1e-3
+    with pytest.raises(ValueError):
+        oracle.burn(c["net"], c["state"], 1.0, RTOL, ATOL, retry=(1e-6, 1e-10, 10, "numeric"))
+
+
 # ------------------------------------------------------ brute force: Radau IIA
 
 def test_radau_is_third_order():
