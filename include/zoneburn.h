@@ -78,6 +78,7 @@ enum { ZB_FP64 = 0, ZB_MIXED = 1 };               /* zb_opts.precision */
 enum { ZB_MAP_AUTO = 0 };                          /* zb_opts.mapping: else lanes per zone 1..64 */
 enum { ZB_JAC_EVERY_STEP = 0, ZB_JAC_REUSE = 1 };  /* zb_opts.jac_policy */
 enum { ZB_BDF = 0, ZB_RKC = 1 };                   /* zb_opts.integrator */
+enum { ZB_RETRY_JAC_ANALYTIC = 0, ZB_RETRY_JAC_FD = 1 };   /* zb_opts.retry_jac */
 
 typedef struct {
     int32_t max_steps;   /* accepted steps per zone before ZB_ZONE_MAXSTEPS (<= 0: 100000) */
@@ -111,7 +112,13 @@ typedef struct {
                             statuses, start, end clamp, abundance constraint and retry; counters
                             nst, nfe, nje (one bound per attempt), netf.  FP64 only (no LU):
                             ZB_EINVAL with ZB_MIXED.  jac_policy does not apply. */
-    int32_t reserved;
+    int32_t retry_jac;   /* the Jacobian of the retry run (the paper, Software design: a retry
+                            may use another Jacobian approximation).  ZB_RETRY_JAC_ANALYTIC (0):
+                            the analytic one, as in the first run.  ZB_RETRY_JAC_FD (1): forward
+                            differences, column j = (f(y + d_j e_j) - f(y)) / d_j with
+                            d_j = 2^-26 max(|y_j|, atol + rtol |y_j|) taken as (y_j + d_j) - y_j;
+                            each one adds nv to the zone's nfe.  BDF only: ZB_EINVAL with ZB_RKC
+                            when retry is on. */
 } zb_opts;
 
 /* Create a context on HIP device `device` (allocates a small device workspace). */

@@ -37,11 +37,15 @@ namespace zb {
 
 // ----------------------------------------------------------------- lane ops
 
+// Orders one lane's LDS stores before other lanes' later LDS loads.  Every workgroup
+// is a single wave, and the LDS performs one wave's accesses in issue order, so a
+// wavefront-scope fence suffices: it keeps the compiler from moving LDS accesses
+// across it and emits no wait for outstanding stores.
 __device__ __forceinline__ void lds_fence()
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <int CTRL>
@@ -276,12 +280,9 @@ __device__ __forceinline__ T gbcast_lds(T v, bool owner, double *slot)
 {
     if constexpr (L == 1) return v;
     if (owner) *slot = (double)v;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    lds_fence();
     T r = (T)*slot;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
+    lds_fence();
     return r;
 }
 
@@ -397,6 +398,7 @@ struct Zone {
     double src[RPL];            // constant source of the zone (0 without one)
     double rtol, atol;          // tolerances of the current run (the retry may loosen them)
     int max_steps, tries;
+    int fdj;                    // Jacobian by finite differences (a retry option)
     // iteration-matrix state for the VODE-style reuse (jac_policy 1)
     double gamma_m;             // gamma the factors in M were formed with
     double cs[RPL];             // column scale of the factors (mixed: the error weight then)
@@ -574,6 +576,47 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
         fo[s] = fi + z.src[s];
     }
 
+}
+
+// Forward-difference Jacobian at y, the alternative Jacobian approximation of a
+// zone-by-zone retry: column j = (f(y + d_j e_j) - f(y)) / d_j with
+// d_j = 2^-26 max(|y_j|, atol + rtol |y_j|) replaced by (y_j + d_j) - y_j, so that it is
+// exactly the change applied.  Leaves f(y) in fo and the rows where eval<true> leaves
+// them; the nv perturbed evaluations are counted in nfe.
+template <int NVP, int L, class LT>
+__device__ __forceinline__ void fd_jacobian(const Ctx &c, Zone<NVP, L, LT> &z,
+                                            const double (&yv)[Zone<NVP, L, LT>::RPL],
+                                            double (&fo)[Zone<NVP, L, LT>::RPL])
+{
+    constexpr int RPL = Zone<NVP, L, LT>::RPL;
+    constexpr int JS = NVP + 1;
+    double *jb = c.S + c.lay.jbuf;
+    eval<false>(c, z, yv, fo);
+    const int nv = c.net.nv;
+    for (int j = 0; j < nv; ++j) {
+        double yp[RPL], fp[RPL];
+        double dj = 0.0;
+        bool own = false;
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) {
+            const double y = yv[s];
+            yp[s] = y;
+            if (row_of<NVP, L>(c, s) == j) {
+                const double d = 0x1p-26 * fmax(fabs(y), z.atol + z.rtol * fabs(y));
+                yp[s] = y + d;
+                dj = yp[s] - y;
+                own = true;
+            }
+        }
+        dj = gbcast<L>(dj, own);
+        eval<false>(c, z, yp, fp);
+#pragma unroll
+        for (int s = 0; s < RPL; ++s) {
+            const int i = row_of<NVP, L>(c, s);
+            if (i < nv) jb[i * JS + j] = (fp[s] - fo[s]) / dj;
+        }
+        z.nfe++;
+    }
 }
 
 // M = I - gamma J from the Jacobian rows in LDS (left there by eval<true>), in
@@ -1017,7 +1060,10 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
             new_j = group_uniform<L>(new_m && (!z.have_j || z.nst >= z.nst_j + 50 || drc >= 0.2));
         }
         if (new_j) {
-            eval<true>(c, z, z.Z[0], z.f);
+            if (group_uniform<L>(z.fdj != 0))
+                fd_jacobian(c, z, z.Z[0], z.f);
+            else
+                eval<true>(c, z, z.Z[0], z.f);
             z.nje++;
             z.have_j = 1;
             z.nst_j = z.nst;
@@ -1410,6 +1456,8 @@ template <int NVP, int L, int JP>
 constexpr int min_waves_per_eu()
 {
     // the reuse kernels keep the factors live across steps: bounded to two waves too
+    // the 8-row kernel fits three waves with a Jacobian every step
+    if (NVP == 8 && L == 8 && JP == 0) return 3;
     return ((NVP >= 48 && L == 64) || (JP == 1 && L >= 16)) ? 2 : 1;
 }
 
@@ -1445,6 +1493,7 @@ void burn_kernel(BurnArgs A)
                 z.atol = c.atol;
                 z.max_steps = A.max_steps;
                 z.tries = 0;
+                z.fdj = 0;
                 int st = zone_start(c, z);
                 if (st == RUNNING)
                     need = false;
@@ -1480,6 +1529,7 @@ void burn_kernel(BurnArgs A)
                     z.atol = A.retry_atol;
                     z.max_steps = A.retry_max_steps;
                     z.tries = 1;
+                    z.fdj = A.retry_jac;
                     st = zone_start(c, z);
                     if (st == RUNNING) continue;
                 } else if (st == ZB_ZONE_OK && z.tries > 0) {

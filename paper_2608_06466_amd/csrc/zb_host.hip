@@ -283,14 +283,14 @@ int zbh::blocks_per_cu(const KernelInfo *k, int max_nr)
 // MAXSEG device counters the launch clears first; nfail: failed-zone counter.
 namespace {
 struct RunOpts {
-    int max_steps, retry, retry_max_steps, jac_policy;
+    int max_steps, retry, retry_max_steps, jac_policy, retry_jac;
     double retry_rtol, retry_atol;
 };
 }  // namespace
 
 static RunOpts run_opts(const zb_opts *o)
 {
-    RunOpts r{100000, 0, 100000, 0, 0.0, 0.0};
+    RunOpts r{100000, 0, 100000, 0, 0, 0.0, 0.0};
     if (o && o->max_steps > 0) r.max_steps = o->max_steps;
     if (o) r.jac_policy = o->jac_policy;
     if (o && o->retry) {
@@ -298,6 +298,7 @@ static RunOpts run_opts(const zb_opts *o)
         r.retry_rtol = o->retry_rtol;
         r.retry_atol = o->retry_atol;
         r.retry_max_steps = o->retry_max_steps > 0 ? o->retry_max_steps : r.max_steps;
+        r.retry_jac = o->retry_jac;
     }
     return r;
 }
@@ -333,6 +334,7 @@ static zb_err launch_segments(zb_context *ctx, const KernelInfo *k, const zb_seg
     A.retry_max_steps = ro.retry_max_steps;
     A.retry_rtol = ro.retry_rtol;
     A.retry_atol = ro.retry_atol;
+    A.retry_jac = ro.retry_jac;
     A.queue = queue;
     A.nfail = nfail;
 
@@ -391,6 +393,11 @@ static zb_err plan_groups(zb_context *ctx, const zb_segment *segs, int n, const 
         return fail(ZB_EINVAL, "integrator %d", opts->integrator);
     const bool rkc = opts && opts->integrator == ZB_RKC;
     if (rkc && prec == ZB_MIXED) return fail(ZB_EINVAL, "the RKC integrator has no LU: use ZB_FP64");
+    if (opts && opts->retry && opts->retry_jac != ZB_RETRY_JAC_ANALYTIC &&
+        opts->retry_jac != ZB_RETRY_JAC_FD)
+        return fail(ZB_EINVAL, "retry_jac %d", opts->retry_jac);
+    if (opts && opts->retry && rkc && opts->retry_jac == ZB_RETRY_JAC_FD)
+        return fail(ZB_EINVAL, "the finite-difference retry Jacobian is a BDF option");
     const int jac = rkc ? 2 : (opts ? opts->jac_policy : 0);
     for (int i = 0; i < n; ++i) {
         zb_err e = check_segment(ctx, segs[i]);

@@ -50,6 +50,7 @@ struct BurnArgs {
     int max_nr;                    // largest reaction count of the segments (sizes the LDS)
     int max_steps;
     int retry, retry_max_steps;    // zone-by-zone retry of failed zones (0: off)
+    int retry_jac;                 // retry Jacobian: 0 analytic, 1 finite differences
     double retry_rtol, retry_atol;
     unsigned long long *queue;     // [nseg] next zone of each segment (zeroed before the launch)
     unsigned long long *nfail;     // zones that ended with a non-OK status

@@ -392,6 +392,10 @@ extern "C" zb_err zb_server_create(zb_context *ctx, const zb_server_opts *so, zb
     if (bo.integrator != ZB_BDF && bo.integrator != ZB_RKC) return fail(ZB_EINVAL, "integrator %d", bo.integrator);
     if (bo.integrator == ZB_RKC && bo.precision == ZB_MIXED)
         return fail(ZB_EINVAL, "the RKC integrator has no LU: use ZB_FP64");
+    if (bo.retry && bo.retry_jac != ZB_RETRY_JAC_ANALYTIC && bo.retry_jac != ZB_RETRY_JAC_FD)
+        return fail(ZB_EINVAL, "retry_jac %d", bo.retry_jac);
+    if (bo.retry && bo.integrator == ZB_RKC && bo.retry_jac == ZB_RETRY_JAC_FD)
+        return fail(ZB_EINVAL, "the finite-difference retry Jacobian is a BDF option");
     DeviceGuard g(ctx->device);
     zb_server *S = new (std::nothrow) zb_server();
     if (!S) return fail(ZB_ENOMEM, "host allocation failed");

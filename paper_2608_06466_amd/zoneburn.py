@@ -40,7 +40,7 @@ class _Opts(C.Structure):
     _fields_ = [("max_steps", C.c_int32), ("precision", C.c_int32), ("mapping", C.c_int32),
                 ("retry", C.c_int32), ("retry_rtol", C.c_double), ("retry_atol", C.c_double),
                 ("retry_max_steps", C.c_int32), ("jac_policy", C.c_int32),
-                ("integrator", C.c_int32), ("reserved", C.c_int32)]
+                ("integrator", C.c_int32), ("retry_jac", C.c_int32)]
 
 
 class _Segment(C.Structure):
@@ -185,7 +185,8 @@ BDF, RKC = 0, 1
 
 
 def _opts(precision, lanes, max_steps, retry=None, jac_policy=0, integrator=0):
-    """retry: None, or (rtol, atol, max_steps) of the zone-by-zone retry of failed zones.
+    """retry: None, or (rtol, atol, max_steps[, jac]) of the zone-by-zone retry of failed
+    zones, jac "analytic" (default) or "fd" (finite-difference Jacobian in the retry).
     jac_policy: 0 Jacobian and LU every step attempt, 1 VODE-style reuse.
     integrator: "bdf" (0) or "rkc" (1)."""
     prec = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}[precision]
@@ -193,8 +194,12 @@ def _opts(precision, lanes, max_steps, retry=None, jac_policy=0, integrator=0):
     it = {"bdf": 0, "rkc": 1, 0: 0, 1: 1}[integrator]
     if retry is None:
         return _Opts(int(max_steps or 0), prec, int(lanes or 0), 0, 0.0, 0.0, 0, jp, it, 0)
+    rjac = retry[3] if len(retry) > 3 else "analytic"
+    rj = {"analytic": 0, "fd": 1, 0: 0, 1: 1}.get(rjac)
+    if rj is None:
+        raise ValueError("retry jac must be 'analytic' or 'fd'")
     return _Opts(int(max_steps or 0), prec, int(lanes or 0), 1, float(retry[0]), float(retry[1]),
-                 int(retry[2]), jp, it, 0)
+                 int(retry[2]), jp, it, rj)
 
 
 def _check_state(net, state):
@@ -262,7 +267,7 @@ def _segments(segments):
 def burn_batch(ctx, segments, precision="fp64", lanes=0, max_steps=0, stream=None, retry=None,
                jac_policy=0, integrator="bdf"):
     """segments: list of dicts(net, state, dt, rtol, atol, rate_scale=None, status=None,
-    stats=None, source=None); retry: None or (rtol, atol, max_steps)."""
+    stats=None, source=None); retry: None or (rtol, atol, max_steps[, jac])."""
     arr = _segments(segments)
     o = _opts(precision, lanes, max_steps, retry, jac_policy, integrator)
     _check(lib().zb_burn_batch(ctx.h, arr, len(segments), C.byref(o), _stream_handle(stream)),

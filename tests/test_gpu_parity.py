@@ -487,3 +487,63 @@ def test_rkc_rejects_mixed_precision(zbm):
                 precision="mixed", integrator="rkc")
     assert e.value.code == zb.EINVAL
     net.close()
+
+
+@pytest.mark.parametrize("which", ["config2", "nv22", "nv48"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fd_retry_parity(zbm, which, precision):
+    """A 5-step cap fails nearly every zone, so the retry with the finite-difference Jacobian
+    (at the first run's tolerances) integrates them all: the oracle's statuses (6), results
+    within the widened bar, and, in the retry pass, nv RHS evaluations per Jacobian on top of
+    the integrator's own (2 at the start, one per Newton iteration, one per order-1 restart
+    after three error failures)."""
+    zb, ctx = zbm
+    if which == "config2":
+        net_d = W.config2_network()
+        st = W.random_zones(net_d, 128, seed=779)
+    else:
+        k = {"nv22": 1, "nv48": 2}[which]
+        ns, R, seed = W.CONFIG3_NETS[k]
+        net_d = W.random_network(ns, R, seed)
+        st = W.random_zones(net_d, [0, 96, 32][k], seed=778, T_range=W.CONFIG3_T_RANGE,
+                            T_dist="loguniform")
+    nv = net_d["n_species"] + net_d["thermal"]
+    retry = (1e-8, 1e-12, 100000, "fd")
+    ref = oracle.burn(net_d, st, 1.0, 1e-8, 1e-12, max_steps=5, retry=retry)
+    fine = oracle.burn(net_d, st, 1.0, 1e-10, 1e-14, max_steps=10000000)
+    net = zb.Network(ctx, net_d)
+    t = torch.tensor(st, device="cuda:0")
+    status, stats = zb.burn(ctx, net, t, 1.0, 1e-8, 1e-12, precision=precision, max_steps=5,
+                            retry=retry)
+    assert zb.sync(ctx) == 0
+    g = (t.cpu().numpy(), status.cpu().numpy(), stats.cpu().numpy())
+    gfine = run_gpu(zb, ctx, net_d, st, 1.0, 1e-10, 1e-14, precision=precision,
+                    max_steps=10000000, net=net)
+    first = run_gpu(zb, ctx, net_d, st, 1.0, 1e-8, 1e-12, precision=precision, max_steps=5,
+                    net=net)
+    retried = ref[1] == 6
+    assert retried.sum() >= 0.9 * len(st)
+    assert np.array_equal(g[1], ref[1])
+    as_ok = lambda r: (r[0], np.where(r[1] == 6, 0, r[1]).astype(np.int32), r[2])
+    check(f"{which} fd retry {precision}", as_ok(g), (as_ok(ref), fine), 1e-8, 1e-12, nv, gfine)
+    for total, once in ((g[2], first[2]), (ref[2], oracle.burn(net_d, st, 1.0, 1e-8, 1e-12,
+                                                                max_steps=5)[2])):
+        p = (total - once)[retried]
+        extra = p[:, 1] - 2 - p[:, 4] - nv * p[:, 2]
+        assert np.all(extra >= 0) and np.all(3 * extra <= p[:, 5]), extra[extra != 0][:5]
+    net.close()
+
+
+def test_fd_retry_options_are_checked(zbm):
+    """The finite-difference retry Jacobian is a BDF option (no Jacobian-based solve in RKC),
+    and only 'analytic' and 'fd' exist."""
+    zb, ctx = zbm
+    c = W.config2(4)
+    net = zb.Network(ctx, c["net"])
+    t = torch.tensor(c["state"], device="cuda:0")
+    with pytest.raises(zb.ZoneburnError) as e:
+        zb.burn(ctx, net, t, 1.0, 1e-6, 1e-10, integrator="rkc", retry=(1e-4, 1e-8, 1000, "fd"))
+    assert e.value.code == zb.EINVAL
+    with pytest.raises(ValueError):
+        zb.burn(ctx, net, t, 1.0, 1e-6, 1e-10, retry=(1e-4, 1e-8, 1000, "numeric"))
+    net.close()
