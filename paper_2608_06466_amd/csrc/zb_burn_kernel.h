@@ -48,6 +48,17 @@ __device__ __forceinline__ void lds_fence()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Pivot reciprocal.  FP64 divides (correctly rounded).  FP32 (the mixed-precision LU, an
+// approximate factorisation the Newton iteration absorbs) takes the hardware reciprocal and
+// one Newton step, within about an ulp, instead of the longer IEEE division sequence; a zero
+// pivot still yields a non-finite factor and so a failed Newton iteration.
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(fmaf(-x, r, 1.0f), r, r);
+}
+
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v)
 {
@@ -709,7 +720,7 @@ __device__ __forceinline__ void lu_factor(const Ctx &c, Zone<NVP, L, LT> &z)
             // Whole-wave zone: the pivot lane p is wave-uniform, so the pivot row is
             // read from its registers with v_readlane (8 columns at a time) instead of
             // going through LDS.
-            const LT rinv = LT(1) / lane_read(z.M[0][k], p);
+            const LT rinv = recip(lane_read(z.M[0][k], p));
             if (c.gl == p) {
                 z.pstep[0] = k;
                 z.dinv[0] = rinv;
@@ -742,7 +753,7 @@ __device__ __forceinline__ void lu_factor(const Ctx &c, Zone<NVP, L, LT> &z)
             });
         }
         lds_fence();
-        LT rinv = LT(1) / prow[k];
+        LT rinv = recip(prow[k]);
         sfor<0, RPL>([&](auto S) {
             int i = row_of<NVP, L>(c, S);
             if (i == p) {
