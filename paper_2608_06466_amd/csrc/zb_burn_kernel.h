@@ -59,6 +59,23 @@ __device__ __forceinline__ float recip(float x)
     return fmaf(fmaf(-x, r, 1.0f), r, r);
 }
 
+// Load from global memory.  The network tables reach the kernel through generic
+// pointers, which compile to flat loads; those also count against the LDS wait counter,
+// so every LDS wait would wait for them too.
+typedef int zb_v4i __attribute__((ext_vector_type(4)));
+typedef double zb_v2d __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ int4 gload(const int4 *p)
+{
+    const zb_v4i v = *(const __attribute__((address_space(1))) zb_v4i *)p;
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ double4 gload(const double4 *p)
+{
+    const __attribute__((address_space(1))) zb_v2d *q = (const __attribute__((address_space(1))) zb_v2d *)p;
+    const zb_v2d a = q[0], b = q[1];
+    return make_double4(a.x, a.y, b.x, b.y);
+}
+
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v)
 {
@@ -499,9 +516,20 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
         iT = 1.0 / T;
     }
     double sT = 0.0, sTT = 0.0;
+    // the next reaction's parameters are loaded while the current one is processed
+    int4 nix = make_int4(0, -1, 0, 0);
+    double4 npr = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (c.gl < N.nr) {
+        nix = gload(N.rct + c.gl);
+        npr = gload(N.par + c.gl);
+    }
     for (int r = c.gl; r < N.nr; r += L) {
-        int4 ix = N.rct[r];
-        double4 pr = N.par[r];
+        const int4 ix = nix;
+        const double4 pr = npr;
+        if (r + L < N.nr) {
+            nix = gload(N.rct + r + L);
+            npr = gload(N.par + r + L);
+        }
         // sign-aware mass action: w = s k Ya Yb with s = -1 when both reactants are
         // negative (k Ya |Ya| for A + A), so a negative abundance is pulled back to 0
         const double ya = ybuf[ix.x];
@@ -553,8 +581,11 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
                     jit = fma(nu, rx[3 * nr + r], jit);
                 }
             };
-            for (int e = 0; e < N.inv_len / 2; ++e) {
-                const int4 en = lst[e];
+            const int n2 = N.inv_len / 2;
+            int4 nen = n2 > 0 ? gload(lst) : make_int4(-1, 0, -1, 0);
+            for (int e = 0; e < n2; ++e) {
+                const int4 en = nen;
+                if (e + 1 < n2) nen = gload(lst + e + 1);
                 if (en.x < 0) break;
                 entry(en.x, en.y);
                 if (en.z < 0) break;
@@ -571,8 +602,17 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
                     const double d = ((fl & 1) ? rx[nr + r] : 0.0) + ((fl & 2) ? rx[2 * nr + r] : 0.0);
                     v = fma(q, d, v);
                 };
+                int4 n0 = make_int4(-1, 0, 0, 0), n1 = make_int4(-1, 0, 0, 0);
+                if (N.rea_len > 0) {
+                    n0 = gload(rl);
+                    n1 = gload(rl + 1);
+                }
                 for (int e = 0; e < N.rea_len; e += 2) {
-                    const int4 e0 = rl[e], e1 = rl[e + 1];
+                    const int4 e0 = n0, e1 = n1;
+                    if (e + 2 < N.rea_len) {
+                        n0 = gload(rl + e + 2);
+                        n1 = gload(rl + e + 3);
+                    }
                     if (e0.x < 0) break;
                     tent(e0);
                     if (e1.x < 0) break;
