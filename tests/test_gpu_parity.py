@@ -489,9 +489,10 @@ def test_rkc_rejects_mixed_precision(zbm):
     net.close()
 
 
-@pytest.mark.parametrize("which", ["config2", "nv22", "nv48"])
+@pytest.mark.parametrize("which,jac_policy", [("config2", 0), ("nv22", 0), ("nv48", 0),
+                                               ("config2", 1)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_fd_retry_parity(zbm, which, precision):
+def test_fd_retry_parity(zbm, which, jac_policy, precision):
     """A 5-step cap fails nearly every zone, so the retry with the finite-difference Jacobian
     (at the first run's tolerances) integrates them all: the oracle's statuses (6), results
     within the widened bar, and, in the retry pass, nv RHS evaluations per Jacobian on top of
@@ -509,28 +510,40 @@ def test_fd_retry_parity(zbm, which, precision):
                             T_dist="loguniform")
     nv = net_d["n_species"] + net_d["thermal"]
     retry = (1e-8, 1e-12, 100000, "fd")
-    ref = oracle.burn(net_d, st, 1.0, 1e-8, 1e-12, max_steps=5, retry=retry)
+    ref = oracle.burn(net_d, st, 1.0, 1e-8, 1e-12, max_steps=5, retry=retry,
+                      jac_policy=jac_policy)
     fine = oracle.burn(net_d, st, 1.0, 1e-10, 1e-14, max_steps=10000000)
     net = zb.Network(ctx, net_d)
     t = torch.tensor(st, device="cuda:0")
     status, stats = zb.burn(ctx, net, t, 1.0, 1e-8, 1e-12, precision=precision, max_steps=5,
-                            retry=retry)
+                            retry=retry, jac_policy=jac_policy)
     assert zb.sync(ctx) == 0
     g = (t.cpu().numpy(), status.cpu().numpy(), stats.cpu().numpy())
     gfine = run_gpu(zb, ctx, net_d, st, 1.0, 1e-10, 1e-14, precision=precision,
                     max_steps=10000000, net=net)
-    first = run_gpu(zb, ctx, net_d, st, 1.0, 1e-8, 1e-12, precision=precision, max_steps=5,
-                    net=net)
+    t1 = torch.tensor(st, device="cuda:0")
+    s1, st1 = zb.burn(ctx, net, t1, 1.0, 1e-8, 1e-12, precision=precision, max_steps=5,
+                      jac_policy=jac_policy)
+    zb.sync(ctx)
+    first = (t1.cpu().numpy(), s1.cpu().numpy(), st1.cpu().numpy())
     retried = ref[1] == 6
     assert retried.sum() >= 0.9 * len(st)
     assert np.array_equal(g[1], ref[1])
     as_ok = lambda r: (r[0], np.where(r[1] == 6, 0, r[1]).astype(np.int32), r[2])
-    check(f"{which} fd retry {precision}", as_ok(g), (as_ok(ref), fine), 1e-8, 1e-12, nv, gfine)
-    for total, once in ((g[2], first[2]), (ref[2], oracle.burn(net_d, st, 1.0, 1e-8, 1e-12,
-                                                                max_steps=5)[2])):
+    check(f"{which} fd retry {precision} policy {jac_policy}", as_ok(g), (as_ok(ref), fine),
+          1e-8, 1e-12, nv, gfine)
+    once_ref = oracle.burn(net_d, st, 1.0, 1e-8, 1e-12, max_steps=5, jac_policy=jac_policy)[2]
+    for total, once in ((g[2], first[2]), (ref[2], once_ref)):
         p = (total - once)[retried]
-        extra = p[:, 1] - 2 - p[:, 4] - nv * p[:, 2]
-        assert np.all(extra >= 0) and np.all(3 * extra <= p[:, 5]), extra[extra != 0][:5]
+        if jac_policy == 0:
+            extra = p[:, 1] - 2 - p[:, 4] - nv * p[:, 2]
+            assert np.all(extra >= 0) and np.all(3 * extra <= p[:, 5]), extra[extra != 0][:5]
+        else:
+            # reuse: far fewer Jacobians than steps, each still nv evaluations beyond the
+            # integrator's own (one per Newton iteration, one per attempt that refreshes J
+            # before its Newton pass, 2 at the start, restarts)
+            assert p[:, 2].sum() * 4 < p[:, 0].sum()
+            assert np.all(p[:, 1] >= 2 + p[:, 4] + nv * p[:, 2])
     net.close()
 
 
