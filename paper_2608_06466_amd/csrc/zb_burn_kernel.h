@@ -567,18 +567,37 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
             const int4 *lst = (const int4 *)(N.inv + i * N.inv_len);
             double jit = 0.0;
             double *jrow = jb + i * JS;
-            auto entry = [&](int x, int y) {
-                const int r = x & 0xffff;
-                const double nu = (double)((x >> 16) - 8);
-                fi = fma(nu, rx[r], fi);
-                if (WANTJ) {
-                    const int a = y & 0xff, b = (y >> 8) - 1;
-                    __hip_atomic_fetch_add(jrow + a, nu * rx[nr + r], __ATOMIC_RELAXED,
+            auto jadd = [&](int y, double nu, double da, double db) {
+                const int a = y & 0xff, b = (y >> 8) - 1;
+                __hip_atomic_fetch_add(jrow + a, nu * da, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (b >= 0)
+                    __hip_atomic_fetch_add(jrow + b, nu * db, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
-                    if (b >= 0)
-                        __hip_atomic_fetch_add(jrow + b, nu * rx[2 * nr + r], __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
-                    jit = fma(nu, rx[3 * nr + r], jit);
+            };
+            // A pair of entries: the second is taken under a predicate (a padding entry
+            // reads slot 0 and adds nothing), so the LDS reads of both go out together.
+            auto pair = [&](int4 en) {
+                const bool has1 = en.z >= 0;
+                const int r0 = en.x & 0xffff, r1 = has1 ? (en.z & 0xffff) : 0;
+                const double nu0 = (double)((en.x >> 16) - 8);
+                const double nu1 = (double)((en.z >> 16) - 8);
+                const double w0 = rx[r0], w1 = rx[r1];
+                double p0 = 0.0, p1 = 0.0, q0 = 0.0, q1 = 0.0, t0 = 0.0, t1 = 0.0;
+                if (WANTJ) {
+                    p0 = rx[nr + r0]; p1 = rx[nr + r1];
+                    q0 = rx[2 * nr + r0]; q1 = rx[2 * nr + r1];
+                    t0 = rx[3 * nr + r0]; t1 = rx[3 * nr + r1];
+                }
+                fi = fma(nu0, w0, fi);
+                if (has1) fi = fma(nu1, w1, fi);
+                if (WANTJ) {
+                    jadd(en.y, nu0, p0, q0);
+                    jit = fma(nu0, t0, jit);
+                    if (has1) {
+                        jadd(en.w, nu1, p1, q1);
+                        jit = fma(nu1, t1, jit);
+                    }
                 }
             };
             const int n2 = N.inv_len / 2;
@@ -587,19 +606,18 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
                 const int4 en = nen;
                 if (e + 1 < n2) nen = gload(lst + e + 1);
                 if (en.x < 0) break;
-                entry(en.x, en.y);
+                pair(en);
                 if (en.z < 0) break;
-                entry(en.z, en.w);
             }
             if (WANTJ && N.thermal) {
                 jrow[N.ns] = jit;
                 // T row: sum over the reactions that consume species i of q_r dw_r/dY_i
                 const int4 *rl = N.rea + i * N.rea_len;
                 double v = 0.0;
-                auto tent = [&](int4 en) {
-                    const int r = en.x & 0xffff, fl = en.x >> 16;
+                auto tent = [&](int4 en, double da, double db) {
+                    const int fl = en.x >> 16;
                     const double q = __longlong_as_double(((long long)en.w << 32) | (unsigned)en.z);
-                    const double d = ((fl & 1) ? rx[nr + r] : 0.0) + ((fl & 2) ? rx[2 * nr + r] : 0.0);
+                    const double d = ((fl & 1) ? da : 0.0) + ((fl & 2) ? db : 0.0);
                     v = fma(q, d, v);
                 };
                 int4 n0 = make_int4(-1, 0, 0, 0), n1 = make_int4(-1, 0, 0, 0);
@@ -614,9 +632,14 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
                         n1 = gload(rl + e + 3);
                     }
                     if (e0.x < 0) break;
-                    tent(e0);
-                    if (e1.x < 0) break;
-                    tent(e1);
+                    // both entries' reads together; the second under a predicate
+                    const bool has1 = e1.x >= 0;
+                    const int r0 = e0.x & 0xffff, r1 = has1 ? (e1.x & 0xffff) : 0;
+                    const double a0 = rx[nr + r0], b0 = rx[2 * nr + r0];
+                    const double a1 = rx[nr + r1], b1 = rx[2 * nr + r1];
+                    tent(e0, a0, b0);
+                    if (!has1) break;
+                    tent(e1, a1, b1);
                 }
                 jb[N.ns * JS + i] = v;
             }
