@@ -560,3 +560,30 @@ def test_fd_retry_options_are_checked(zbm):
     with pytest.raises(ValueError):
         zb.burn(ctx, net, t, 1.0, 1e-6, 1e-10, retry=(1e-4, 1e-8, 1000, "numeric"))
     net.close()
+
+
+@pytest.mark.parametrize("lanes", [1, 4])
+def test_fd_retry_robertson_rows_per_lane(zbm, lanes):
+    """The finite-difference retry on Robertson with one lane per zone (four rows a lane)
+    and four lanes per zone: a 20-step cap fails every zone, the retry at the same
+    tolerances matches the oracle's (statuses 6, results within the bar)."""
+    zb, ctx = zbm
+    c = W.config1(512)
+    retry = (1e-8, 1e-12, 100000, "fd")
+    ref = oracle.burn(c["net"], c["state"], c["dt"], 1e-8, 1e-12, scale=c["scale"], max_steps=20,
+                      retry=retry)
+    fine = oracle.burn(c["net"], c["state"], c["dt"], 1e-10, 1e-14, scale=c["scale"],
+                       max_steps=10000000)
+    net = zb.Network(ctx, c["net"])
+    t = torch.tensor(c["state"], device="cuda:0")
+    sc = torch.tensor(c["scale"], device="cuda:0")
+    status, stats = zb.burn(ctx, net, t, c["dt"], 1e-8, 1e-12, rate_scale=sc, lanes=lanes,
+                            max_steps=20, retry=retry)
+    assert zb.sync(ctx) == 0
+    g = (t.cpu().numpy(), status.cpu().numpy(), stats.cpu().numpy())
+    gfine = run_gpu(zb, ctx, c["net"], c["state"], c["dt"], 1e-10, 1e-14, scale=c["scale"],
+                    lanes=lanes, max_steps=10000000, net=net)
+    assert np.all(ref[1] == 6) and np.array_equal(g[1], ref[1])
+    as_ok = lambda r: (r[0], np.where(r[1] == 6, 0, r[1]).astype(np.int32), r[2])
+    check(f"robertson fd retry L{lanes}", as_ok(g), (as_ok(ref), fine), 1e-8, 1e-12, 3, gfine)
+    net.close()
