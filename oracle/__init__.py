@@ -55,7 +55,11 @@ def lib():
         _lib.orc_rkc_stages.restype = i
         _lib.orc_rkc_stages.argtypes = [d, d]
         _lib.orc_burn_ex.restype = i
-        _lib.orc_burn_ex.argtypes = [p, p, C.c_int64, p, p, d, d, d, i, i, p, p, p, i]
+        _lib.orc_burn_ex.argtypes = [p, p, C.c_int64, p, p, d, d, d, i, i, i, p, p, p, i]
+        _lib.orc_vc_xi.argtypes = [i, d, p, i, p]
+        _lib.orc_vc_lcoef.argtypes = [i, p, p]
+        _lib.orc_vc_steps.restype = i
+        _lib.orc_vc_steps.argtypes = [p, p, i, i, p, p, i, p, p]
         _lib.orc_burn_zone.restype = i
         _lib.orc_burn_zone.argtypes = [p, p, p, d, d, d, i, p]
         _lib.orc_rhs.argtypes = [p, p, p, p]
@@ -113,14 +117,17 @@ class _Retry(C.Structure):
 
 
 def burn(net, state, dt, rtol, atol, scale=None, max_steps=100000, nthreads=None, source=None,
-         retry=None, jac_policy=0):
+         retry=None, jac_policy=0, form="fixed"):
     """Burn a copy of state [zones][ns+1]; returns (state, status[zones], stats[zones,7]).
 
     source: optional constant per-zone term [zones][ns+1] added to the right-hand side.
     retry: optional (rtol, atol, max_steps[, jac]) for a second run of every failed zone
     from its input, jac "analytic" (default) or "fd" (finite-difference Jacobian); such a
     zone then reports status 6 when the retry succeeds.
-    jac_policy: 0 Jacobian and LU every step attempt, 1 VODE-style reuse."""
+    jac_policy: 0 Jacobian and LU every step attempt, 1 VODE-style reuse.
+    form: "fixed" (fixed-leading-coefficient BDF) or "variable" (variable-coefficient)."""
+    if form not in ("fixed", "variable"):
+        raise ValueError("form must be 'fixed' or 'variable'")
     n = _as_net(net)
     st = np.array(state, dtype=np.float64, copy=True, order="C")
     zones = st.shape[0]
@@ -143,8 +150,8 @@ def burn(net, state, dt, rtol, atol, scale=None, max_steps=100000, nthreads=None
             raise ValueError("retry jac must be 'analytic' or 'fd'")
         rt = _Retry(1, float(retry[0]), float(retry[1]), int(retry[2]), int(rjac == "fd"))
     lib().orc_burn_ex(n.ref, _dp(st), zones, _dp(sc), _dp(src), dt, rtol, atol, int(max_steps),
-                      int(jac_policy), None if rt is None else C.byref(rt), _ip(status), _ip(stats),
-                      int(nthreads))
+                      int(jac_policy), int(form == "variable"), None if rt is None else C.byref(rt),
+                      _ip(status), _ip(stats), int(nthreads))
     return st, status, stats
 
 
@@ -184,6 +191,37 @@ def fd_jac(net, y, rtol, atol, scale=None, source=None):
     src = None if source is None else np.ascontiguousarray(source, dtype=np.float64)
     lib().orc_fd_jac(n.ref, _dp(sc), _dp(src), _dp(y), float(rtol), float(atol), _dp(J))
     return J
+
+
+def vc_xi(q, h, hist):
+    """xi_1..xi_{q+1} of the variable-coefficient form (index 0 unused)."""
+    hist = np.ascontiguousarray(hist, dtype=np.float64)
+    xi = np.zeros(q + 2)
+    lib().orc_vc_xi(q, float(h), _dp(hist) if hist.size else None, int(hist.size), _dp(xi))
+    return xi
+
+
+def vc_lcoef(q, xi):
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    l = np.zeros(q + 1)
+    lib().orc_vc_lcoef(q, _dp(xi), _dp(l))
+    return l
+
+
+def vc_steps(net, Z, q, hs, hist, scale=None):
+    """Fixed order q over the step sizes hs with the variable-coefficient form; Z [q+1][nv]
+    in units of hs[0]; hist: past step sizes, newest first.  Returns (ys [n][nv], Z)."""
+    n = _as_net(net)
+    Z = np.array(Z, dtype=np.float64, copy=True, order="C")
+    hs = np.ascontiguousarray(hs, dtype=np.float64)
+    hist = np.ascontiguousarray(hist, dtype=np.float64)
+    ys = np.zeros((len(hs), n.nv))
+    sc = None if scale is None else np.ascontiguousarray(scale, dtype=np.float64)
+    r = lib().orc_vc_steps(n.ref, _dp(sc), q, len(hs), _dp(hs), _dp(hist) if hist.size else None,
+                           int(hist.size), _dp(Z), _dp(ys))
+    if r:
+        raise RuntimeError(f"Newton failed at step {r - 1}")
+    return ys, Z
 
 
 def lu(A):

@@ -36,6 +36,10 @@
  *           (NONFINITE).  A failed zone keeps its last accepted state.
  *  End      The step that would reach dt (within 4 eps relative) is shortened
  *           to land on dt exactly.
+ *  Form     (option) The variable-coefficient form takes l and the error divisor
+ *           from the step history instead (coef_variable).  Order changes keep the
+ *           fixed coefficients: they happen only after q+1 steps of equal size, where
+ *           the two forms coincide.
  */
 #include <float.h>
 #include <math.h>
@@ -60,10 +64,18 @@ static double wrms(int nv, const double *v, const double *w)
     return sqrt(s / nv);
 }
 
-/* Estimated local error of the accepted BDF-q step: dy ~ h^(q+1) y^(q+1), error constant 1/(q+1). */
-static double local_error(int nv, int q, const double *dy, const double *w)
+/* Coefficients of one step attempt: l(q) (l_1 = 1, gamma = h l_0) and the divisor of the
+   local-error estimate.  The fixed-leading-coefficient form takes l from prod (1 + x/i) and
+   divides by q + 1; the variable-coefficient form (below) from the step history. */
+typedef struct {
+    double l[ORC_QMAX + 1];
+    double ediv;
+} coef_t;
+
+/* Estimated local error of the accepted BDF-q step: |dy| / (q+1), or / xi_{q+1}. */
+static double local_error(int nv, const coef_t *C, const double *dy, const double *w)
 {
-    return wrms(nv, dy, w) / (q + 1);
+    return wrms(nv, dy, w) / C->ediv;
 }
 
 /* f(y) = network RHS + the zone's constant source (the simplified-SDC coupling of a
@@ -96,6 +108,45 @@ void orc_stirling(int n, double *c)
         p[0] = m * p[0];
     }
     for (int j = 0; j <= n; j++) c[j] = p[j];
+}
+
+static void coef_fixed(int q, coef_t *C)
+{
+    orc_lcoef(q, C->l);
+    C->ediv = q + 1;
+}
+
+/* Variable-coefficient BDF (the form of VODE): with xi_i = (t_{n+1} - t_{n+1-i}) / h the
+   corrector direction is prod_{i<=q} (1 + x/xi_i), the polynomial that vanishes at the q
+   past points, so the corrected Nordsieck polynomial keeps interpolating the last q+1
+   values and the step is the BDF on the actual (uneven) grid; normalised to l_1 = 1.  The
+   error estimate divides by xi_{q+1} (q + 1 at constant steps).  hist[m] = t_{n-m} -
+   t_{n-m-1} for the nh known past steps; unknown ones count as steps of the current h, so
+   the start and a restart use the fixed coefficients. */
+void orc_vc_xi(int q, double h, const double *hist, int nh, double *xi)
+{
+    double acc = 1.0;
+    xi[1] = 1.0;
+    for (int i = 2; i <= q + 1; i++) {
+        acc += (i - 2 < nh) ? hist[i - 2] / h : 1.0;
+        xi[i] = acc;
+    }
+}
+
+void orc_vc_lcoef(int q, const double *xi, double *l)
+{
+    double p[ORC_QMAX + 2] = {1.0};
+    for (int i = 1; i <= q; i++)
+        for (int j = i; j >= 1; j--) p[j] += p[j - 1] / xi[i];
+    for (int j = 0; j <= q; j++) l[j] = p[j] / p[1];
+}
+
+static void coef_variable(int q, double h, const double *hist, int nh, coef_t *C)
+{
+    double xi[ORC_QMAX + 2];
+    orc_vc_xi(q, h, hist, nh, xi);
+    orc_vc_lcoef(q, xi, C->l);
+    C->ediv = xi[q + 1];
 }
 
 /* Raise q -> q+1: the new leading term is dy / (q+1)!, added along x(x+1)...(x+q). */
@@ -213,12 +264,12 @@ static void eval_jac(const sys_t *S, jac_t *J, const double *y, orc_stats *st)
 }
 
 /* The Newton iterations with the current M.  Returns 0 on convergence, 1 on failure. */
-static int newton_iter(const sys_t *S, const jac_t *J, int q, double h, const double *Z,
+static int newton_iter(const sys_t *S, const jac_t *J, const coef_t *C, double h, const double *Z,
                        const double *w, double *y, double *dy, orc_stats *st)
 {
     int nv = S->nv;
-    double l[ORC_QMAX + 1], f[ORC_NVMAX], b[ORC_NVMAX];
-    orc_lcoef(q, l);
+    double f[ORC_NVMAX], b[ORC_NVMAX];
+    const double *l = C->l;
     const double gamma = h * l[0];
     const double rc = gamma / J->gamma_m;          /* 1 with a matrix formed at this gamma */
     const double cscale = (rc != 1.0) ? 2.0 / (1.0 + rc) : 1.0;
@@ -250,16 +301,14 @@ static int newton_iter(const sys_t *S, const jac_t *J, int q, double h, const do
 
 /* One Newton solve of the corrector.  On success dy holds y - y_pred and y the new value.
    Returns 0 on convergence, 1 on failure. */
-static int newton(const sys_t *S, jac_t *J, int q, double h, const double *Z, const double *w,
-                  double *y, double *dy, orc_stats *st)
+static int newton(const sys_t *S, jac_t *J, const coef_t *C, double h, const double *Z,
+                  const double *w, double *y, double *dy, orc_stats *st)
 {
-    double l[ORC_QMAX + 1];
-    orc_lcoef(q, l);
-    const double gamma = h * l[0];
+    const double gamma = h * C->l[0];
     if (J->policy == 0) {
         eval_jac(S, J, Z, st);
         form_lu(S, J, gamma, st);
-        return newton_iter(S, J, q, h, Z, w, y, dy, st);
+        return newton_iter(S, J, C, h, Z, w, y, dy, st);
     }
     int fresh = 0;   /* J evaluated at this attempt's prediction */
     const double drc = J->have_m ? fabs(gamma / J->gamma_m - 1.0) : 1.0;
@@ -270,19 +319,18 @@ static int newton(const sys_t *S, jac_t *J, int q, double h, const double *Z, co
         }
         form_lu(S, J, gamma, st);
     }
-    if (newton_iter(S, J, q, h, Z, w, y, dy, st) == 0) return 0;
+    if (newton_iter(S, J, C, h, Z, w, y, dy, st) == 0) return 0;
     if (fresh) return 1;
     /* failure with a Jacobian from an earlier step: refresh it here and retry once */
     eval_jac(S, J, Z, st);
     form_lu(S, J, gamma, st);
-    return newton_iter(S, J, q, h, Z, w, y, dy, st);
+    return newton_iter(S, J, C, h, Z, w, y, dy, st);
 }
 
 /* Corrector update of the history after an accepted step. */
-static void correct(int nv, int q, double *Z, const double *y, const double *dy)
+static void correct(int nv, int q, const coef_t *C, double *Z, const double *y, const double *dy)
 {
-    double l[ORC_QMAX + 1];
-    orc_lcoef(q, l);
+    const double *l = C->l;
     for (int i = 0; i < nv; i++) {
         double e = dy[i] / l[0];
         for (int j = 1; j <= q; j++) Z[(size_t)j * nv + i] += l[j] * e;
@@ -293,18 +341,18 @@ static void correct(int nv, int q, double *Z, const double *y, const double *dy)
 int orc_burn_zone(const orc_net *net, double *row, const double *scale, double dt, double rtol,
                   double atol, int max_steps, orc_stats *st)
 {
-    return orc_burn_zone_ex(net, row, scale, NULL, dt, rtol, atol, max_steps, 0, 0, st);
+    return orc_burn_zone_ex(net, row, scale, NULL, dt, rtol, atol, max_steps, 0, 0, 0, st);
 }
 
 int orc_burn_zone_src(const orc_net *net, double *row, const double *scale, const double *src,
                       double dt, double rtol, double atol, int max_steps, orc_stats *st)
 {
-    return orc_burn_zone_ex(net, row, scale, src, dt, rtol, atol, max_steps, 0, 0, st);
+    return orc_burn_zone_ex(net, row, scale, src, dt, rtol, atol, max_steps, 0, 0, 0, st);
 }
 
 int orc_burn_zone_ex(const orc_net *net, double *row, const double *scale, const double *src,
                      double dt, double rtol, double atol, int max_steps, int jac_policy,
-                     int fd_jac, orc_stats *st)
+                     int fd_jac, int vc, orc_stats *st)
 {
     sys_t S = {net, scale, orc_nvar(net), src};
     jac_t J;
@@ -343,6 +391,9 @@ int orc_burn_zone_ex(const orc_net *net, double *row, const double *scale, const
     int q = 1, nequal = 0, nef = 0, ncf = 0, status = ORC_OK;
     double t = 0.0;
     for (int i = 0; i < nv; i++) { Z[nv + i] = h * f0[i]; dyprev[i] = 0.0; }
+    double hist[ORC_QMAX];   /* accepted step sizes, newest first (variable-coefficient form) */
+    int nh = 0;
+    coef_t C;
 
     for (;;) {
         if (st->nst >= max_steps) { status = ORC_MAXSTEPS; break; }
@@ -357,8 +408,12 @@ int orc_burn_zone_ex(const orc_net *net, double *row, const double *scale, const
         for (int i = 0; i < nv; i++) w[i] = atol + rtol * fabs(Z[i]);
         memcpy(Zs, Z, sizeof(double) * (size_t)(q + 1) * nv);
         predict(nv, q, Z);
+        if (vc)
+            coef_variable(q, h, hist, nh, &C);
+        else
+            coef_fixed(q, &C);
 
-        if (newton(&S, &J, q, h, Z, w, y, dy, st)) {
+        if (newton(&S, &J, &C, h, Z, w, y, dy, st)) {
             memcpy(Z, Zs, sizeof(double) * (size_t)(q + 1) * nv);
             st->ncf++;
             if (++ncf >= 10) { status = ORC_CONV; break; }
@@ -369,7 +424,7 @@ int orc_burn_zone_ex(const orc_net *net, double *row, const double *scale, const
             continue;
         }
 
-        double err = local_error(nv, q, dy, w);
+        double err = local_error(nv, &C, dy, w);
         /* Non-negativity (an inequality constraint on the abundances, as in CVODE): a step
            that takes a species below -atol is rejected like an error-test failure and cut
            to 0.9 of the fraction of it that keeps every species at or above -atol. */
@@ -391,6 +446,7 @@ int orc_burn_zone_ex(const orc_net *net, double *row, const double *scale, const
             h *= eta;
             if (nef >= 3) {
                 q = 1;
+                nh = 0;      /* the restarted history is a tangent, not past values */
                 rhs(&S, Z, f0, st);
                 for (int i = 0; i < nv; i++) Z[nv + i] = h * f0[i];
             } else {
@@ -402,7 +458,10 @@ int orc_burn_zone_ex(const orc_net *net, double *row, const double *scale, const
         }
 
         /* ---- accept ---- */
-        correct(nv, q, Z, y, dy);
+        correct(nv, q, &C, Z, y, dy);
+        for (int m = ORC_QMAX - 1; m > 0; m--) hist[m] = hist[m - 1];
+        hist[0] = h;
+        if (nh < ORC_QMAX) nh++;
         t = last ? dt : t + h;
         st->nst++;
         nequal++;
@@ -460,9 +519,46 @@ int orc_fixed_steps(const orc_net *net, const double *scale, int q, double h, in
     for (int n = 0; n < nsteps; n++) {
         for (int i = 0; i < nv; i++) w[i] = 1e-12 + 1e-8 * fabs(Z[i]);
         predict(nv, q, Z);
-        if (newton(&S, &J, q, h, Z, w, y, dy, &st)) return n + 1;
-        if (errs) errs[n] = local_error(nv, q, dy, w);
-        correct(nv, q, Z, y, dy);
+        coef_t C;
+        coef_fixed(q, &C);
+        if (newton(&S, &J, &C, h, Z, w, y, dy, &st)) return n + 1;
+        if (errs) errs[n] = local_error(nv, &C, dy, w);
+        correct(nv, q, &C, Z, y, dy);
+        for (int i = 0; i < nv; i++) ys[(size_t)n * nv + i] = Z[i];
+    }
+    memcpy(Zio, Z, sizeof(double) * (size_t)(q + 1) * nv);
+    return 0;
+}
+
+/* Fixed order q over the step sizes hs[0..nsteps) with the variable-coefficient form: Z (in
+   units of hs[0]) is rescaled between steps, hist0 holds the nh0 past step sizes (newest
+   first).  ys receives y after each step.  Returns 0, or 1 + the step whose Newton failed. */
+int orc_vc_steps(const orc_net *net, const double *scale, int q, int nsteps, const double *hs,
+                 const double *hist0, int nh0, double *Zio, double *ys)
+{
+    sys_t S = {net, scale, orc_nvar(net), NULL};
+    int nv = S.nv;
+    orc_stats st;
+    jac_t J;
+    memset(&J, 0, sizeof J);
+    memset(&st, 0, sizeof st);
+    double Z[(ORC_QMAX + 2) * ORC_NVMAX], w[ORC_NVMAX], y[ORC_NVMAX], dy[ORC_NVMAX];
+    double hist[ORC_QMAX];
+    int nh = nh0 < ORC_QMAX ? nh0 : ORC_QMAX;
+    for (int m = 0; m < nh; m++) hist[m] = hist0[m];
+    memcpy(Z, Zio, sizeof(double) * (size_t)(q + 1) * nv);
+    for (int n = 0; n < nsteps; n++) {
+        const double h = hs[n];
+        if (n > 0) rescale(nv, q, Z, h / hs[n - 1]);
+        for (int i = 0; i < nv; i++) w[i] = 1e-12 + 1e-8 * fabs(Z[i]);
+        predict(nv, q, Z);
+        coef_t C;
+        coef_variable(q, h, hist, nh, &C);
+        if (newton(&S, &J, &C, h, Z, w, y, dy, &st)) return n + 1;
+        correct(nv, q, &C, Z, y, dy);
+        for (int m = ORC_QMAX - 1; m > 0; m--) hist[m] = hist[m - 1];
+        hist[0] = h;
+        if (nh < ORC_QMAX) nh++;
         for (int i = 0; i < nv; i++) ys[(size_t)n * nv + i] = Z[i];
     }
     memcpy(Zio, Z, sizeof(double) * (size_t)(q + 1) * nv);
@@ -492,13 +588,14 @@ int orc_burn_retry(const orc_net *net, double *state, int64_t zones, const doubl
                    const double *source, double dt, double rtol, double atol, int max_steps,
                    const orc_retry *retry, int32_t *status, int32_t *stats, int nthreads)
 {
-    return orc_burn_ex(net, state, zones, scale, source, dt, rtol, atol, max_steps, 0, retry, status,
-                       stats, nthreads);
+    return orc_burn_ex(net, state, zones, scale, source, dt, rtol, atol, max_steps, 0, 0, retry,
+                       status, stats, nthreads);
 }
 
 int orc_burn_ex(const orc_net *net, double *state, int64_t zones, const double *scale,
                 const double *source, double dt, double rtol, double atol, int max_steps,
-                int jac_policy, const orc_retry *retry, int32_t *status, int32_t *stats, int nthreads)
+                int jac_policy, int form, const orc_retry *retry, int32_t *status, int32_t *stats,
+                int nthreads)
 {
     if (orc_check_net(net)) return -1;
     int row = net->ns + 1;
@@ -511,12 +608,12 @@ int orc_burn_ex(const orc_net *net, double *state, int64_t zones, const double *
         const double *sc = scale ? scale + z * net->nr : NULL;
         const double *sr = source ? source + z * row : NULL;
         memcpy(in, y, sizeof(double) * row);
-        int s = orc_burn_zone_ex(net, y, sc, sr, dt, rtol, atol, max_steps, jac_policy, 0, &st);
+        int s = orc_burn_zone_ex(net, y, sc, sr, dt, rtol, atol, max_steps, jac_policy, 0, form, &st);
         if (s != ORC_OK && retry && retry->enabled) {
             orc_stats st2;
             memcpy(y, in, sizeof(double) * row);
             s = orc_burn_zone_ex(net, y, sc, sr, dt, retry->rtol, retry->atol, retry->max_steps,
-                                 jac_policy, retry->jac, &st2);
+                                 jac_policy, retry->jac, form, &st2);
             if (s == ORC_OK) s = ORC_OK_RETRY;
             st.nst += st2.nst; st.nfe += st2.nfe; st.nje += st2.nje; st.nlu += st2.nlu;
             st.nni += st2.nni; st.netf += st2.netf; st.ncf += st2.ncf;

@@ -104,9 +104,15 @@ int orc_burn_retry(const orc_net *net, double *state, int64_t zones, const doubl
 
 /* jac_policy 0: Jacobian and LU on every step attempt (the default everywhere above).
    jac_policy 1: VODE-style reuse of the iteration matrix and the Jacobian (rules in bdf.c). */
+/* vc: 0 the fixed-leading-coefficient form (the default everywhere above), 1 the
+   variable-coefficient form (l and the error divisor from the step history, bdf.c). */
 int orc_burn_zone_ex(const orc_net *net, double *row, const double *scale, const double *src,
                      double dt, double rtol, double atol, int max_steps, int jac_policy,
-                     int fd_jac, orc_stats *st);
+                     int fd_jac, int vc, orc_stats *st);
+void orc_vc_xi(int q, double h, const double *hist, int nh, double *xi);
+void orc_vc_lcoef(int q, const double *xi, double *l);
+int orc_vc_steps(const orc_net *net, const double *scale, int q, int nsteps, const double *hs,
+                 const double *hist0, int nh0, double *Zio, double *ys);
 /* Finite-difference Jacobian of f (the network RHS plus src, if any) at y, row-major
    [nv][nv]: column j is (f(y + d_j e_j) - f(y)) / d_j with d_j = 2^-26 max(|y_j|,
    atol + rtol |y_j|), taken as (y_j + d_j) - y_j. */
@@ -114,7 +120,7 @@ void orc_fd_jac(const orc_net *net, const double *scale, const double *src, cons
                 double rtol, double atol, double *J);
 int orc_burn_ex(const orc_net *net, double *state, int64_t zones, const double *scale,
                 const double *source, double dt, double rtol, double atol, int max_steps,
-                int jac_policy, const orc_retry *retry, int32_t *status, int32_t *stats,
-                int nthreads);
+                int jac_policy, int form, const orc_retry *retry, int32_t *status,
+                int32_t *stats, int nthreads);
 
 #endif

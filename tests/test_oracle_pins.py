@@ -8,6 +8,7 @@ two-body kinetics, first-order Arrhenius decay), conservation laws, an
 independent brute-force Radau IIA integrator and scipy's Radau at tight
 tolerance.
 """
+import functools
 import math
 import os
 from fractions import Fraction
@@ -471,6 +472,23 @@ def test_source_moves_the_species_sum_by_its_own_sum():
 
 # ------------------------------------------------ non-negativity constraint
 
+@functools.lru_cache(maxsize=None)
+def _radau_robertson():
+    """scipy's Radau at rtol 1e-12 on Robertson over [0, 1e5] (computed once per session)."""
+    net = oracle.Net(W.robertson_network())
+    return solve_ivp(lambda t, y: oracle.rhs(net, y), (0, 1e5), [1.0, 0.0, 0.0], method="Radau",
+                     rtol=1e-12, atol=1e-20, jac=lambda t, y: oracle.jac(net, y)).y[:, -1]
+
+
+@functools.lru_cache(maxsize=None)
+def _radau_config2(z):
+    """scipy's Radau at rtol 1e-12 on zone z of the first 96 benchmark zones over dt = 1."""
+    c2 = W.config2(96)
+    return solve_ivp(lambda t, y: oracle.rhs(c2["net"], y), (0.0, 1.0), c2["state"][z, :14],
+                     method="Radau", rtol=1e-12, atol=1e-20,
+                     jac=lambda t, y: oracle.jac(c2["net"], y)).y[:, -1]
+
+
 def test_loose_tolerance_zones_match_scipy_radau():
     """At rtol 1e-6 zone 43 of this input drains a species linearly through zero: every higher
     derivative is small, so the local-error test alone accepts a step to -1.5e-3 (the true
@@ -482,11 +500,7 @@ def test_loose_tolerance_zones_match_scipy_radau():
     assert np.all(status == 0)
     assert out[:, :13].min() >= -1e-10
     for k, z in enumerate(idx):
-        r = solve_ivp(lambda t, y: oracle.rhs(c["net"], y), (0.0, 1.0), c["state"][z, :14],
-                      method="Radau", rtol=1e-12, atol=1e-20,
-                      jac=lambda t, y: oracle.jac(c["net"], y))
-        assert r.status == 0
-        assert gated_err(out[k, :14], r.y[:, -1], rtol=1e-6, atol=1e-10) < 1e-4, z
+        assert gated_err(out[k, :14], _radau_config2(z), rtol=1e-6, atol=1e-10) < 1e-4, z
 
 
 # --------------------------------------- VODE-style Jacobian/LU reuse (policy 1)
@@ -526,19 +540,121 @@ def test_reuse_closed_forms_and_invariants():
 
 def test_reuse_robertson_and_benchmark_zones_match_scipy_radau():
     net = oracle.Net(W.robertson_network())
-    sol = solve_ivp(lambda t, y: oracle.rhs(net, y), (0, 1e5), [1.0, 0.0, 0.0], method="Radau",
-                    rtol=1e-12, atol=1e-20, jac=lambda t, y: oracle.jac(net, y))
     out, status, stats = oracle.burn(net, np.array([[1.0, 0.0, 0.0, 0.0]]), 1e5, RTOL, ATOL,
                                      jac_policy=1)
-    assert status[0] == 0 and gated_err(out[0, :3], sol.y[:, -1]) < 1e-6
+    assert status[0] == 0 and gated_err(out[0, :3], _radau_robertson()) < 1e-6
     assert stats[0, 2] * 4 < stats[0, 0]
     c2 = W.config2(96)
     for z in (3, 43):
-        r = solve_ivp(lambda t, y: oracle.rhs(c2["net"], y), (0.0, 1.0), c2["state"][z, :14],
-                      method="Radau", rtol=1e-12, atol=1e-20, jac=lambda t, y: oracle.jac(c2["net"], y))
         out, status, stats = oracle.burn(c2["net"], c2["state"][z:z + 1], 1.0, RTOL, ATOL, jac_policy=1)
-        assert status[0] == 0 and gated_err(out[0, :14], r.y[:, -1]) < 1e-5, z
+        assert status[0] == 0 and gated_err(out[0, :14], _radau_config2(z)) < 1e-5, z
         assert stats[0, 2] * 5 < stats[0, 0] and stats[0, 3] * 5 < stats[0, 0]
+
+
+# ------------------------------------------- variable-coefficient BDF (VODE's form)
+
+@pytest.mark.parametrize("q", [1, 2, 3, 4, 5])
+def test_vc_coefficients_reduce_to_the_fixed_ones_at_constant_steps(q):
+    h = 0.37
+    for hist in ([], [h] * 5, [h] * q):
+        xi = oracle.vc_xi(q, h, np.array(hist))
+        assert np.array_equal(xi[1:], np.arange(1, q + 2, dtype=float))
+    np.testing.assert_allclose(oracle.vc_lcoef(q, np.arange(q + 2, dtype=float)), oracle.lcoef(q),
+                               rtol=2e-16, atol=0)
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 4, 5])
+def test_vc_direction_vanishes_at_the_past_points(q):
+    """l(x) = sum l_j x^j has l_1 = 1 and its q roots at the past times x = -xi_i (in
+    units of h before the new point): the correction leaves the past values alone."""
+    rng = np.random.default_rng(40 + q)
+    hs = rng.uniform(0.4, 2.5, size=q + 1)          # newest step first
+    h = hs[0]
+    xi = oracle.vc_xi(q, h, hs[1:])
+    np.testing.assert_allclose(xi[1:], np.cumsum(hs[: q + 1]) / h, rtol=1e-15)
+    l = oracle.vc_lcoef(q, xi)
+    assert l[1] == 1.0
+    for i in range(1, q + 1):
+        assert abs(np.polyval(l[::-1], -xi[i])) < 1e-13 * np.abs(l).sum() * xi[i] ** q
+
+
+def _classic_variable_bdf(K, times, ys_past, q):
+    """y at times[-1] from the variable-step BDF-q: the degree-q interpolant through it and the
+    q previous values has derivative K y there (Lagrange basis derivatives, brute force)."""
+    nodes = [times[-1]] + [times[-1 - j] for j in range(1, q + 1)]
+    a = []
+    for j in range(q + 1):
+        if j == 0:
+            a.append(sum(1.0 / (nodes[0] - nodes[m]) for m in range(1, q + 1)))
+        else:
+            num = np.prod([nodes[0] - nodes[m] for m in range(q + 1) if m not in (0, j)])
+            den = np.prod([nodes[j] - nodes[m] for m in range(q + 1) if m != j])
+            a.append(num / den)
+    rhs = -sum(a[j] * ys_past[-j] for j in range(1, q + 1))
+    return np.linalg.solve(a[0] * np.eye(len(rhs)) - K, rhs)
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 4, 5])
+def test_vc_steps_equal_the_classic_variable_step_bdf(q):
+    """Over a random uneven step sequence, the variable-coefficient Nordsieck steps equal the
+    BDF of the actual grid (interpolation through the last q+1 values, derivative = f)."""
+    net = W.linear_network(3, seed=11, k_range=(0.1, 10.0), density=1.0)
+    K = linear_K(net)
+    y0 = np.array([0.5, 0.3, 0.2])
+    rng = np.random.default_rng(7 + q)
+    past = np.concatenate([[0.0], -np.cumsum(rng.uniform(0.02, 0.08, size=q))])  # t_0, t_-1, ...
+    hs = rng.uniform(0.02, 0.08, size=20)
+    ys_hist = np.array([sla.expm(K * t) @ y0 for t in past])
+    h0 = hs[0]
+    Z = _nordsieck_of_interpolant(ys_hist, past / h0)          # x in units of hs[0]
+    hist = -np.diff(past)                                        # newest first
+    ys, _ = oracle.vc_steps(net, Z, q, hs, hist)
+    times = list(past[::-1])
+    vals = list(ys_hist[::-1])
+    ref = []
+    for h in hs:
+        times.append(times[-1] + h)
+        ynew = _classic_variable_bdf(K, times, vals, q)
+        vals.append(ynew)
+        ref.append(ynew)
+    ref = np.array(ref)
+    assert np.max(np.abs(ys - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_vc_burn_linear_network_matches_matrix_exponential(seed):
+    ns = 4 + seed % 3
+    net = W.linear_network(ns, seed)
+    K = linear_K(net)
+    y0 = np.random.default_rng(seed).dirichlet(np.ones(ns))
+    st = np.zeros((1, ns + 1))
+    st[0, :ns] = y0
+    for jp in (0, 1):
+        out, status, _ = oracle.burn(net, st, 10.0, RTOL, ATOL, form="variable", jac_policy=jp)
+        assert status[0] == 0
+        assert gated_err(out[0, :ns], sla.expm(K * 10.0) @ y0) < 1e-6
+        # the species sum drifts only by the rounding the fixed form shows on the same network
+        # (stiff networks, rates up to 1e8, reach ~1e-10 in either form)
+        fixed = oracle.burn(net, st, 10.0, RTOL, ATOL, jac_policy=jp)[0]
+        assert abs(out[0, :ns].sum() - 1.0) <= 10 * abs(fixed[0, :ns].sum() - 1.0) + 1e-13
+
+
+def test_vc_robertson_and_benchmark_zones_match_scipy_radau():
+    net = oracle.Net(W.robertson_network())
+    out, status, stats = oracle.burn(net, np.array([[1.0, 0.0, 0.0, 0.0]]), 1e5, RTOL, ATOL,
+                                     form="variable")
+    assert status[0] == 0 and gated_err(out[0, :3], _radau_robertson()) < 1e-6
+    c2 = W.config2(96)
+    fixed = oracle.burn(c2["net"], c2["state"][:8], 1.0, RTOL, ATOL)
+    var = oracle.burn(c2["net"], c2["state"][:8], 1.0, RTOL, ATOL, form="variable")
+    assert np.all(var[1] == 0)
+    for z in (3, 43):
+        out, status, _ = oracle.burn(c2["net"], c2["state"][z:z + 1], 1.0, RTOL, ATOL, form="variable")
+        assert status[0] == 0 and gated_err(out[0, :14], _radau_config2(z)) < 1e-5, z
+    # the two forms are different methods: same answers to tolerance, different step paths
+    assert not np.array_equal(var[2], fixed[2])
+    with pytest.raises(ValueError):
+        oracle.burn(c2["net"], c2["state"][:2], 1.0, RTOL, ATOL, form="vode")
 
 
 # ------------------------------------------------- Runge-Kutta-Chebyshev (RKC)
@@ -760,11 +876,9 @@ def test_bdf_matches_bruteforce_radau_tiny_batch():
 @pytest.mark.slow
 def test_robertson_matches_scipy_radau():
     net = oracle.Net(W.robertson_network())
-    sol = solve_ivp(lambda t, y: oracle.rhs(net, y), (0, 1e5), [1.0, 0.0, 0.0], method="Radau",
-                    rtol=1e-12, atol=1e-20, jac=lambda t, y: oracle.jac(net, y))
     out, status, _ = oracle.burn(net, np.array([[1.0, 0.0, 0.0, 0.0]]), 1e5, RTOL, ATOL)
     assert status[0] == 0
-    assert gated_err(out[0, :3], sol.y[:, -1]) < 1e-6
+    assert gated_err(out[0, :3], _radau_robertson()) < 1e-6
 
 
 @pytest.mark.slow
