@@ -97,7 +97,7 @@ def headline(args):
     work = torch.empty_like(state0)
     stream = torch.cuda.current_stream()
 
-    def run(precision, steps, warmup, jac_policy=0):
+    def run(precision, steps, warmup, jac_policy=0, integrator="bdf"):
         lanes = zb.get_mapping(ctx, net, precision)
         times, kernel_ms = [], []
         status = stats = None
@@ -109,7 +109,7 @@ def headline(args):
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             status, stats = zb.burn(ctx, net, work, dt, rtol, atol, precision=precision,
-                                    jac_policy=jac_policy)
+                                    jac_policy=jac_policy, integrator=integrator)
             e1.record(stream)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -117,7 +117,8 @@ def headline(args):
             if it >= warmup:
                 times.append(t1 - t0)
                 kernel_ms.append(e0.elapsed_time(e1))
-            print(f"[bench] {precision} jac {jac_policy} step {it - warmup if it >= warmup else 'warmup'}: "
+            print(f"[bench] {precision} jac {jac_policy} {integrator} "
+                  f"step {it - warmup if it >= warmup else 'warmup'}: "
                   f"{(t1 - t0) * 1e3:.1f} ms (kernel {e0.elapsed_time(e1):.1f} ms), failed zones {nfail}",
                   file=sys.stderr, flush=True)
         st = stats.cpu().numpy()
@@ -131,6 +132,8 @@ def headline(args):
     # the VODE-style Jacobian/LU reuse (reported beside the headline method, which takes a
     # Jacobian and an LU on every step)
     res["reuse"] = run("mixed", args.steps, args.warmup, jac_policy=1)
+    # VODE's own configuration: the variable-coefficient BDF form with that reuse
+    res["vode"] = run("mixed", args.steps, args.warmup, jac_policy=1, integrator="bdf_variable")
 
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
@@ -150,6 +153,7 @@ def headline(args):
                     max_steps=int(r["stats"][:, 0].max()))
 
     sm, sf, sr = summary(res["mixed"]), summary(res["fp64"]), summary(res["reuse"])
+    sv = summary(res["vode"])
 
     def roofline(s, precision):
         achieved = s["flops"] / (s["kernel_ms"] * 1e-3) / 1e12
@@ -180,8 +184,12 @@ def headline(args):
         accuracy = {}
         ref_r, ref_r_status, _ = oracle.burn(net_d, state0_np[idx], dt, rtol, atol, nthreads=threads,
                                              jac_policy=1)
-        for prec in ("mixed", "fp64", "reuse"):
-            rs, rst = (ref_r, ref_r_status) if prec == "reuse" else (ref, ref_status)
+        ref_v, ref_v_status, _ = oracle.burn(net_d, state0_np[idx], dt, rtol, atol, nthreads=threads,
+                                             jac_policy=1, form="variable")
+        refs = {"mixed": (ref, ref_status), "fp64": (ref, ref_status),
+                "reuse": (ref_r, ref_r_status), "vode": (ref_v, ref_v_status)}
+        for prec in ("mixed", "fp64", "reuse", "vode"):
+            rs, rst = refs[prec]
             out = res[prec]["out"][idx][:, :nv]
             ok = (rst == 0) & (res[prec]["status"][idx] == 0)
             gated = np.abs(out[ok] - rs[ok, :nv]) / np.maximum(np.abs(rs[ok, :nv]), atol / rtol)
@@ -220,6 +228,14 @@ def headline(args):
                       "lus_per_zone": round(float(res["reuse"]["stats"][:, 3].mean()), 1),
                       "note": "VODE-style reuse of the Jacobian and LU (jac_policy 1); value counts "
                               "OK zones; accuracy against the oracle's reuse policy"},
+        "vode_form": {"value": round(sv["value"], 1), "ms_per_step": round(sv["ms_per_step"], 2),
+                      "kernel_ms": round(sv["kernel_ms"], 2), "precision": "mixed",
+                      "failed_zones": int((res["vode"]["status"] != 0).sum()),
+                      "mean_steps": round(sv["mean_steps"], 1),
+                      "jacobians_per_zone": round(float(res["vode"]["stats"][:, 2].mean()), 1),
+                      "note": "variable-coefficient BDF form with the Jacobian/LU reuse (integrator "
+                              "bdf_variable, jac_policy 1); value counts OK zones; accuracy against "
+                              "the oracle's same configuration"},
         "roofline": roofline(sm, "mixed"),
         "kernel_ms": round(sm["kernel_ms"], 2),
         "zone_steps": {"mean": round(sm["mean_steps"], 1), "max": sm["max_steps"]},

@@ -77,7 +77,7 @@ typedef struct zb_server zb_server;
 enum { ZB_FP64 = 0, ZB_MIXED = 1 };               /* zb_opts.precision */
 enum { ZB_MAP_AUTO = 0 };                          /* zb_opts.mapping: else lanes per zone 1..64 */
 enum { ZB_JAC_EVERY_STEP = 0, ZB_JAC_REUSE = 1 };  /* zb_opts.jac_policy */
-enum { ZB_BDF = 0, ZB_RKC = 1 };                   /* zb_opts.integrator */
+enum { ZB_BDF = 0, ZB_RKC = 1, ZB_BDF_VARIABLE = 2 };   /* zb_opts.integrator */
 enum { ZB_RETRY_JAC_ANALYTIC = 0, ZB_RETRY_JAC_FD = 1 };   /* zb_opts.retry_jac */
 
 typedef struct {
@@ -111,7 +111,14 @@ typedef struct {
                             estimate (12 (y_n - y_{n+1}) + 6 h (F_n + F_{n+1})) / 15).  Same
                             statuses, start, end clamp, abundance constraint and retry; counters
                             nst, nfe, nje (one bound per attempt), netf.  FP64 only (no LU):
-                            ZB_EINVAL with ZB_MIXED.  jac_policy does not apply. */
+                            ZB_EINVAL with ZB_MIXED.  jac_policy does not apply.
+                            ZB_BDF_VARIABLE (2): the BDF in VODE's variable-coefficient form:
+                            with xi_i = (t_{n+1} - t_{n+1-i}) / h over the accepted steps, the
+                            corrector coefficients are those of prod_{i<=q} (1 + x/xi_i) (l_1 =
+                            1) and the error estimate divides by xi_{q+1}, so the step is the
+                            BDF of the actual uneven grid; identical to ZB_BDF at constant steps
+                            (order changes, which follow q+1 equal steps, use the same
+                            coefficients).  Both precisions and both jac_policy values. */
     int32_t retry_jac;   /* the Jacobian of the retry run (the paper, Software design: a retry
                             may use another Jacobian approximation).  ZB_RETRY_JAC_ANALYTIC (0):
                             the analytic one, as in the first run.  ZB_RETRY_JAC_FD (1): forward

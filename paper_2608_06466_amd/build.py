@@ -14,9 +14,15 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libzoneburn.so")
 # the burn-kernel instantiations are spread over several files so they compile in parallel
-SOURCES = ["zb_k48d.hip", "zb_k48f.hip", "zb_k48dr.hip", "zb_k48fr.hip", "zb_k16.hip",
-           "zb_k16r.hip", "zb_k16n.hip", "zb_k24.hip", "zb_k24r.hip", "zb_k32.hip", "zb_k32r.hip",
-           "zb_k04.hip", "zb_k04r.hip", "zb_kc.hip", "zb_kernels.hip", "zb_host.hip", "zb_server.hip"]
+SOURCES = [
+    # the 48-row kernels compile slowest: first, so the parallel build starts them early
+    "zb_k48d.hip", "zb_k48f.hip", "zb_k48dr.hip", "zb_k48fr.hip",
+    "zb_kv_d.hip", "zb_kv_e.hip", "zb_kvr_d.hip", "zb_kvr_e.hip",
+    "zb_k16.hip", "zb_k16r.hip", "zb_k16n.hip", "zb_k24.hip", "zb_k24r.hip", "zb_k32.hip",
+    "zb_k32r.hip", "zb_k04.hip", "zb_k04r.hip", "zb_kc.hip",
+    "zb_kv_a.hip", "zb_kv_b.hip", "zb_kv_c.hip", "zb_kvr_a.hip", "zb_kvr_b.hip", "zb_kvr_c.hip",
+    "zb_kernels.hip", "zb_host.hip", "zb_server.hip",
+]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -339,8 +339,13 @@ __device__ __forceinline__ bool gany(bool b)
     return greduce<L>(b ? 1 : 0, OpMax()) != 0;
 }
 
-// Integration methods (the compile-time third parameter of the burn kernel).
-enum { METHOD_BDF = 0, METHOD_BDF_REUSE = 1, METHOD_RKC = 2 };
+// Integration methods (the compile-time fourth parameter of the burn kernel): the
+// fixed-leading-coefficient BDF with a Jacobian every step or reused, RKC, and the
+// variable-coefficient BDF with either Jacobian policy.
+enum { METHOD_BDF = 0, METHOD_BDF_REUSE = 1, METHOD_RKC = 2, METHOD_BDF_VC = 3,
+       METHOD_BDF_VC_REUSE = 4 };
+constexpr bool method_vc(int m) { return m == METHOD_BDF_VC || m == METHOD_BDF_VC_REUSE; }
+constexpr int method_jac(int m) { return (m == METHOD_BDF_REUSE || m == METHOD_BDF_VC_REUSE) ? 1 : 0; }
 constexpr int RKC_SMAX = 250;
 
 // --------------------------------------------------------- BDF coefficients
@@ -982,7 +987,7 @@ __device__ __forceinline__ void restore_history(const Ctx &c, Zone<NVP, L, LT> &
 enum { RUNNING = -1 };
 
 // Start of a zone: load, Hairer-Norsett-Wanner initial step.  Returns RUNNING or a status.
-template <int NVP, int L, class LT>
+template <bool VC, int NVP, int L, class LT>
 __device__ __forceinline__ int zone_start(const Ctx &c, Zone<NVP, L, LT> &z)
 {
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
@@ -1041,6 +1046,10 @@ __device__ __forceinline__ int zone_start(const Ctx &c, Zone<NVP, L, LT> &z)
     z.nequal = z.nefc = z.ncfc = 0;
 #pragma unroll
     for (int s = 0; s < RPL; ++s) z.Z[1][s] = (c.jac_policy == METHOD_RKC) ? f0[s] : h * f0[s];
+    if constexpr (VC) {
+        if (c.gl == 0) c.S[c.lay.vc + VC_COUNT] = 0.0;   // no step history yet
+        lds_fence();
+    }
     return RUNNING;
 }
 
@@ -1093,7 +1102,48 @@ __device__ __forceinline__ bool newton(const Ctx &c, Zone<NVP, L, LT> &z, double
     return false;
 }
 
-template <int NVP, int L, class LT>
+// Variable-coefficient form: xi_i = (t_{n+1} - t_{n+1-i}) / h from the accepted step sizes
+// in LDS (unknown ones count as steps of the current h), l = coefficients of
+// prod_{i<=q} (1 + x/xi_i) normalised to l_1 = 1, error divisor xi_{q+1}.  Returns l_0 and the
+// divisor; the group's lane 0 leaves l_1..l_QMAX in LDS for the correction.
+__device__ __forceinline__ void vc_coefficients(const Ctx &c, int q, double h, double &l0,
+                                                double &ediv)
+{
+    double *vs = c.S + c.lay.vc;
+    const int nh = (int)vs[VC_COUNT];
+    const double rh = 1.0 / h;
+    double xi[QMAX + 2];
+    xi[1] = 1.0;
+    double acc = 1.0;
+#pragma unroll
+    for (int i = 2; i <= QMAX + 1; ++i) {
+        acc += (i - 2 < nh) ? vs[VC_HIST + i - 2] * rh : 1.0;
+        xi[i] = acc;
+    }
+    double p[QMAX + 1];
+    p[0] = 1.0;
+#pragma unroll
+    for (int j = 1; j <= QMAX; ++j) p[j] = 0.0;
+#pragma unroll
+    for (int i = 1; i <= QMAX; ++i) {
+        if (i <= q) {
+            const double r = 1.0 / xi[i];
+#pragma unroll
+            for (int j = i; j >= 1; --j) p[j] = fma(p[j - 1], r, p[j]);
+        }
+    }
+    const double r1 = 1.0 / p[1];
+    l0 = r1;
+    ediv = xi[2];
+#pragma unroll
+    for (int i = 3; i <= QMAX + 1; ++i) ediv = (i == q + 1) ? xi[i] : ediv;
+    if (c.gl == 0) {
+#pragma unroll
+        for (int j = 1; j <= QMAX; ++j) vs[VC_L + j] = p[j] * r1;
+    }
+}
+
+template <bool VC, int NVP, int L, class LT>
 __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
 {
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
@@ -1118,8 +1168,14 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
 #pragma unroll
                 for (int s = 0; s < RPL; ++s) z.Z[j - 1][s] += z.Z[j][s];
 
-    const double l0 = 1.0 / harmonic(z.q);
     const double h = z.h;
+    double l0, ediv;
+    if constexpr (VC) {
+        vc_coefficients(c, z.q, h, l0, ediv);
+    } else {
+        l0 = 1.0 / harmonic(z.q);
+        ediv = (double)(z.q + 1);
+    }
     const double gamma = h * l0;
     // f at the prediction, and the iteration matrix: formed on every attempt (policy 0),
     // or kept across steps and re-formed by the VODE rules (policy 1).  A second pass,
@@ -1169,7 +1225,7 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
         return RUNNING;
     }
 
-    const double err = wrms(c, z, z.dy) / (double)(z.q + 1);
+    const double err = wrms(c, z, z.dy) / ediv;
     // Non-negativity of the abundances: a step that takes a species below -atol fails
     // like an error test and is cut to 0.9 of its feasible fraction (from the saved Z_0).
     double feas = 1.0;
@@ -1195,6 +1251,11 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
         z.h *= eta;
         if (z.nefc >= 3) {
             z.q = 1;
+            if constexpr (VC) {
+                // the restarted history is a tangent, not past values
+                if (c.gl == 0) c.S[c.lay.vc + VC_COUNT] = 0.0;
+                lds_fence();
+            }
             double f0[RPL];
             eval<false>(c, z, z.Z[0], f0);
             z.nfe++;
@@ -1209,14 +1270,26 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
     }
 
     // accept: Z_j += l_j e with e = dy / l_0, Z_0 = y
-    const double H = harmonic(z.q);
+    const double H = VC ? 1.0 / l0 : harmonic(z.q);
 #pragma unroll
     for (int j = 1; j <= QMAX; ++j) {
         if (j <= z.q) {
-            double lj = lcoef(z.q, j);
+            double lj = VC ? c.S[c.lay.vc + VC_L + j] : lcoef(z.q, j);
 #pragma unroll
             for (int s = 0; s < RPL; ++s) z.Z[j][s] += lj * (z.dy[s] * H);
         }
+    }
+    if constexpr (VC) {
+        // the step just taken joins the history (newest first)
+        lds_fence();
+        if (c.gl == 0) {
+            double *vs = c.S + c.lay.vc;
+#pragma unroll
+            for (int m = QMAX - 1; m > 0; --m) vs[VC_HIST + m] = vs[VC_HIST + m - 1];
+            vs[VC_HIST] = h;
+            vs[VC_COUNT] = fmin(vs[VC_COUNT] + 1.0, (double)QMAX);
+        }
+        lds_fence();
     }
 #pragma unroll
     for (int s = 0; s < RPL; ++s) z.Z[0][s] = z.y[s];
@@ -1492,7 +1565,8 @@ __device__ __forceinline__ T uniform(T v)
 }
 
 // Segment data for the wave (the wave works on one segment at a time, so it is uniform).
-__device__ __forceinline__ void load_segment(Ctx &c, const BurnArgs &A, int seg, int nvp, int nvl)
+__device__ __forceinline__ void load_segment(Ctx &c, const BurnArgs &A, int seg, int nvp, int nvl,
+                                             bool vc)
 {
     // seg is wave-uniform: scalar loads from the kernel-argument segment
     const BurnArgs *pa = (const BurnArgs *)__builtin_amdgcn_kernarg_segment_ptr();
@@ -1515,7 +1589,7 @@ __device__ __forceinline__ void load_segment(Ctx &c, const BurnArgs &A, int seg,
     c.rtol = uniform(S.rtol);
     c.atol = uniform(S.atol);
     c.dt = uniform(S.dt);
-    c.lay = lds_layout(nvp, nvl, A.max_nr);
+    c.lay = lds_layout(nvp, nvl, A.max_nr, vc);
 }
 
 // Persistent kernel.  Each wave works through the segments in order; within a
@@ -1531,8 +1605,8 @@ constexpr int min_waves_per_eu()
 {
     // the reuse kernels keep the factors live across steps: bounded to two waves too
     // the 8-row kernel fits three waves with a Jacobian every step
-    if (NVP == 8 && L == 8 && JP == 0) return 3;
-    return ((NVP >= 48 && L == 64) || (JP == 1 && L >= 16)) ? 2 : 1;
+    if (NVP == 8 && L == 8 && (JP == METHOD_BDF || JP == METHOD_BDF_VC)) return 3;
+    return ((NVP >= 48 && L == 64) || (method_jac(JP) == 1 && L >= 16)) ? 2 : 1;
 }
 
 template <int NVP, int L, class LT, int JP>
@@ -1548,9 +1622,10 @@ void burn_kernel(BurnArgs A)
     const int g = lane / L;
     Zone<NVP, L, LT> z;
     int seg = 0;
-    c.jac_policy = JP;   // a constant: each policy is its own kernel (the reuse keeps the
+    c.jac_policy = JP == METHOD_RKC ? METHOD_RKC : method_jac(JP);   // a constant: each
+                         // method is its own kernel (the reuse keeps the
                          // factors live across steps, which costs registers)
-    load_segment(c, A, seg, NVP, L * RPL);
+    load_segment(c, A, seg, NVP, L * RPL, method_vc(JP));
     c.S = smem + g * c.lay.total;
     int64_t zones = uniform(A.seg[0].zones);
     bool need = true, dry = false;
@@ -1568,7 +1643,7 @@ void burn_kernel(BurnArgs A)
                 z.max_steps = A.max_steps;
                 z.tries = 0;
                 z.fdj = 0;
-                int st = zone_start(c, z);
+                int st = zone_start<method_vc(JP)>(c, z);
                 if (st == RUNNING)
                     need = false;
                 else
@@ -1577,7 +1652,7 @@ void burn_kernel(BurnArgs A)
         }
         if (__ballot(!dry) == 0) {
             if (++seg >= A.nseg) break;
-            load_segment(c, A, seg, NVP, L * RPL);
+            load_segment(c, A, seg, NVP, L * RPL, method_vc(JP));
             c.S = smem + g * c.lay.total;
             {
                 const BurnArgs *pa = (const BurnArgs *)__builtin_amdgcn_kernarg_segment_ptr();
@@ -1588,7 +1663,7 @@ void burn_kernel(BurnArgs A)
             continue;
         }
         if (!need) {
-            int st = (JP == METHOD_RKC) ? zone_attempt_rkc(c, z) : zone_attempt(c, z);
+            int st = (JP == METHOD_RKC) ? zone_attempt_rkc(c, z) : zone_attempt<method_vc(JP)>(c, z);
             if (st != RUNNING) {
                 if (st != ZB_ZONE_OK && A.retry && z.tries == 0) {
                     // Zone-by-zone retry with the retry tolerances, from the zone's input
@@ -1604,7 +1679,7 @@ void burn_kernel(BurnArgs A)
                     z.max_steps = A.retry_max_steps;
                     z.tries = 1;
                     z.fdj = A.retry_jac;
-                    st = zone_start(c, z);
+                    st = zone_start<method_vc(JP)>(c, z);
                     if (st == RUNNING) continue;
                 } else if (st == ZB_ZONE_OK && z.tries > 0) {
                     st = ZB_ZONE_OK_RETRY;
@@ -1619,5 +1694,7 @@ void burn_kernel(BurnArgs A)
 #define ZB_K(NVP, L, LT, MIX) {NVP, L, MIX, 0, (const void *)&burn_kernel<NVP, L, LT, 0>}
 #define ZB_KR(NVP, L, LT, MIX) {NVP, L, MIX, 1, (const void *)&burn_kernel<NVP, L, LT, 1>}
 #define ZB_KC(NVP, L) {NVP, L, 0, 2, (const void *)&burn_kernel<NVP, L, double, 2>}
+#define ZB_KV(NVP, L, LT, MIX) {NVP, L, MIX, 3, (const void *)&burn_kernel<NVP, L, LT, 3>}
+#define ZB_KVR(NVP, L, LT, MIX) {NVP, L, MIX, 4, (const void *)&burn_kernel<NVP, L, LT, 4>}
 
 }  // namespace zb

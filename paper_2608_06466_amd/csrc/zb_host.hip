@@ -266,7 +266,7 @@ static size_t launch_lds(const KernelInfo *k, int max_nr)
 {
     const int G = 64 / k->lanes;
     const int rpl = (k->nvp + k->lanes - 1) / k->lanes;
-    const LdsLayout lay = lds_layout(k->nvp, k->lanes * rpl, max_nr);
+    const LdsLayout lay = lds_layout(k->nvp, k->lanes * rpl, max_nr, k->jac >= 3);
     return (size_t)G * lay.total * sizeof(double);
 }
 
@@ -389,7 +389,8 @@ static zb_err plan_groups(zb_context *ctx, const zb_segment *segs, int n, const 
         return fail(ZB_EINVAL, "retry needs finite retry_rtol > 0 and retry_atol > 0");
     if (opts && opts->jac_policy != ZB_JAC_EVERY_STEP && opts->jac_policy != ZB_JAC_REUSE)
         return fail(ZB_EINVAL, "jac_policy %d", opts->jac_policy);
-    if (opts && opts->integrator != ZB_BDF && opts->integrator != ZB_RKC)
+    if (opts && opts->integrator != ZB_BDF && opts->integrator != ZB_RKC &&
+        opts->integrator != ZB_BDF_VARIABLE)
         return fail(ZB_EINVAL, "integrator %d", opts->integrator);
     const bool rkc = opts && opts->integrator == ZB_RKC;
     if (rkc && prec == ZB_MIXED) return fail(ZB_EINVAL, "the RKC integrator has no LU: use ZB_FP64");
@@ -398,7 +399,7 @@ static zb_err plan_groups(zb_context *ctx, const zb_segment *segs, int n, const 
         return fail(ZB_EINVAL, "retry_jac %d", opts->retry_jac);
     if (opts && opts->retry && rkc && opts->retry_jac == ZB_RETRY_JAC_FD)
         return fail(ZB_EINVAL, "the finite-difference retry Jacobian is a BDF option");
-    const int jac = rkc ? 2 : (opts ? opts->jac_policy : 0);
+    const int jac = method_of(opts);
     for (int i = 0; i < n; ++i) {
         zb_err e = check_segment(ctx, segs[i]);
         if (e != ZB_OK) return e;

@@ -49,6 +49,15 @@ struct Workspace {
 };
 
 const zb::KernelInfo *find_kernel(int nv, int lanes, int mixed, int jac);
+
+// Kernel method of validated options: 0/1 fixed-coefficient BDF (Jacobian every step /
+// reused), 2 RKC, 3/4 variable-coefficient BDF (every step / reused).
+inline int method_of(const zb_opts *o)
+{
+    if (!o) return 0;
+    if (o->integrator == ZB_RKC) return 2;
+    return o->jac_policy + (o->integrator == ZB_BDF_VARIABLE ? 3 : 0);
+}
 int lanes_for(zb_context *ctx, const zb_network *net, int prec, const zb_opts *o);
 zb_err check_segment(zb_context *ctx, const zb_segment &s);
 // Validates the segments and launches them (one persistent launch per kernel

@@ -58,11 +58,17 @@ struct BurnArgs {
 
 // Per-group LDS layout (in doubles).  Everything a zone group exchanges lives here.
 struct LdsLayout {
-    int xch, cnt, zs, ybuf, wbuf, prow, ks, rx, jbuf, total;
+    int xch, cnt, zs, ybuf, wbuf, prow, ks, rx, jbuf, vc, total;
 };
 
+// Variable-coefficient BDF slots (kernels of that form only): the accepted step sizes,
+// newest first, their count, the corrector coefficients l_0..l_QMAX of the current attempt
+// and its error divisor.
+constexpr int VC_HIST = 0, VC_COUNT = QMAX, VC_L = QMAX + 1, VC_EDIV = 2 * QMAX + 2,
+              VC_SLOTS = 2 * QMAX + 4;
+
 // nvl = lanes per zone x rows per lane (>= nvp): one slot per lane and local row.
-__host__ __device__ inline LdsLayout lds_layout(int nvp, int nvl, int nr)
+__host__ __device__ inline LdsLayout lds_layout(int nvp, int nvl, int nr, bool vc)
 {
     LdsLayout o;
     int p = 0;
@@ -76,6 +82,7 @@ __host__ __device__ inline LdsLayout lds_layout(int nvp, int nvl, int nr)
     p = (p + 1) & ~1;
     o.rx = p;   p += 4 * nr;          // w, dw/dYa, dw/dYb, dw/dT: four columns of nr
     o.jbuf = p; p += nvp * (nvp + 1); // Jacobian rows with an odd stride (no bank conflicts)
+    o.vc = p;   p += vc ? VC_SLOTS : 0;
     o.total = (p + 1) & ~1;
     return o;
 }

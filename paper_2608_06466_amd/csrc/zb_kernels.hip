@@ -15,6 +15,16 @@ int kernels_32(const KernelInfo **out);
 int kernels_48d(const KernelInfo **out);
 int kernels_48f(const KernelInfo **out);
 int kernels_04r(const KernelInfo **out);
+int kernels_v_a(const KernelInfo **out);
+int kernels_v_b(const KernelInfo **out);
+int kernels_v_c(const KernelInfo **out);
+int kernels_v_d(const KernelInfo **out);
+int kernels_v_e(const KernelInfo **out);
+int kernels_vr_a(const KernelInfo **out);
+int kernels_vr_b(const KernelInfo **out);
+int kernels_vr_c(const KernelInfo **out);
+int kernels_vr_d(const KernelInfo **out);
+int kernels_vr_e(const KernelInfo **out);
 int kernels_16r(const KernelInfo **out);
 int kernels_24r(const KernelInfo **out);
 int kernels_32r(const KernelInfo **out);
@@ -56,6 +66,16 @@ int kernel_table(const KernelInfo **out)
         add(kernels_32r);
         add(kernels_48dr);
         add(kernels_48fr);
+        add(kernels_v_a);
+        add(kernels_v_b);
+        add(kernels_v_c);
+        add(kernels_v_d);
+        add(kernels_v_e);
+        add(kernels_vr_a);
+        add(kernels_vr_b);
+        add(kernels_vr_c);
+        add(kernels_vr_d);
+        add(kernels_vr_e);
         add(kernels_rkc);
         return t;
     }();

@@ -389,7 +389,8 @@ extern "C" zb_err zb_server_create(zb_context *ctx, const zb_server_opts *so, zb
         return fail(ZB_EINVAL, "retry needs finite retry_rtol > 0 and retry_atol > 0");
     if (bo.jac_policy != ZB_JAC_EVERY_STEP && bo.jac_policy != ZB_JAC_REUSE)
         return fail(ZB_EINVAL, "jac_policy %d", bo.jac_policy);
-    if (bo.integrator != ZB_BDF && bo.integrator != ZB_RKC) return fail(ZB_EINVAL, "integrator %d", bo.integrator);
+    if (bo.integrator != ZB_BDF && bo.integrator != ZB_RKC && bo.integrator != ZB_BDF_VARIABLE)
+        return fail(ZB_EINVAL, "integrator %d", bo.integrator);
     if (bo.integrator == ZB_RKC && bo.precision == ZB_MIXED)
         return fail(ZB_EINVAL, "the RKC integrator has no LU: use ZB_FP64");
     if (bo.retry && bo.retry_jac != ZB_RETRY_JAC_ANALYTIC && bo.retry_jac != ZB_RETRY_JAC_FD)
@@ -449,7 +450,7 @@ extern "C" zb_err zb_server_submit(zb_server *S, const zb_network *net, const do
     const int row = net->dn.ns + 1;
     const int lanes = lanes_for(S->ctx, net, S->opts.precision, &S->opts);
     const KernelInfo *k = find_kernel(net->dn.nv, lanes, S->opts.precision == ZB_MIXED,
-                                      S->opts.integrator == ZB_RKC ? 2 : S->opts.jac_policy);
+                                      method_of(&S->opts));
     if (!k) return fail(ZB_EUNSUPPORTED, "no kernel for nv=%d with %d lanes", net->dn.nv, lanes);
     auto al = [](size_t b) { return (b + ALIGN - 1) & ~(ALIGN - 1); };
     size_t bytes = al(sizeof(double) * row * (size_t)zones) + al(sizeof(int32_t) * (size_t)zones) +

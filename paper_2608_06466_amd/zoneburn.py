@@ -188,10 +188,10 @@ def _opts(precision, lanes, max_steps, retry=None, jac_policy=0, integrator=0):
     """retry: None, or (rtol, atol, max_steps[, jac]) of the zone-by-zone retry of failed
     zones, jac "analytic" (default) or "fd" (finite-difference Jacobian in the retry).
     jac_policy: 0 Jacobian and LU every step attempt, 1 VODE-style reuse.
-    integrator: "bdf" (0) or "rkc" (1)."""
+    integrator: "bdf" (0), "rkc" (1) or "bdf_variable" (2, VODE's variable-coefficient form)."""
     prec = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}[precision]
     jp = {"every_step": 0, "reuse": 1, 0: 0, 1: 1}[jac_policy]
-    it = {"bdf": 0, "rkc": 1, 0: 0, 1: 1}[integrator]
+    it = {"bdf": 0, "rkc": 1, "bdf_variable": 2, 0: 0, 1: 1, 2: 2}[integrator]
     if retry is None:
         return _Opts(int(max_steps or 0), prec, int(lanes or 0), 0, 0.0, 0.0, 0, jp, it, 0)
     rjac = retry[3] if len(retry) > 3 else "analytic"
@@ -278,11 +278,11 @@ class Graph:
     """A burn of fixed buffers captured once as a HIP graph (zb_graph_*); launch() replays it."""
 
     def __init__(self, ctx, segments, precision="fp64", lanes=0, max_steps=0, retry=None,
-                 jac_policy=0):
+                 jac_policy=0, integrator="bdf"):
         self.ctx = ctx
         self._segs = segments          # the buffers must outlive the graph
         arr = _segments(segments)
-        o = _opts(precision, lanes, max_steps, retry, jac_policy)
+        o = _opts(precision, lanes, max_steps, retry, jac_policy, integrator)
         h = C.c_void_p()
         _check(lib().zb_graph_create(ctx.h, arr, len(segments), C.byref(o), C.byref(h)),
                "zb_graph_create")
@@ -307,11 +307,12 @@ class Server:
     """Continuous-batching burn server (zb_server_*): host inputs in, host results out."""
 
     def __init__(self, ctx, hbm_budget_bytes, precision="fp64", lanes=0, max_steps=0, streams=0,
-                 launches_per_stream=0, slice_zones=0, max_pending=0, retry=None, jac_policy=0):
+                 launches_per_stream=0, slice_zones=0, max_pending=0, retry=None, jac_policy=0,
+                 integrator="bdf"):
         self.ctx = ctx
         o = _ServerOpts(int(hbm_budget_bytes), int(streams), int(launches_per_stream),
                         int(slice_zones), int(max_pending), 0,
-                        _opts(precision, lanes, max_steps, retry, jac_policy))
+                        _opts(precision, lanes, max_steps, retry, jac_policy, integrator))
         h = C.c_void_p()
         _check(lib().zb_server_create(ctx.h, C.byref(o), C.byref(h)), "zb_server_create")
         self.h = h

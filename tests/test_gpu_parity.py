@@ -587,3 +587,58 @@ def test_fd_retry_robertson_rows_per_lane(zbm, lanes):
     as_ok = lambda r: (r[0], np.where(r[1] == 6, 0, r[1]).astype(np.int32), r[2])
     check(f"robertson fd retry L{lanes}", as_ok(g), (as_ok(ref), fine), 1e-8, 1e-12, 3, gfine)
     net.close()
+
+
+@pytest.mark.parametrize("which,jac_policy", [("config2", 0), ("nv22", 0), ("nv48", 0),
+                                               ("config2", 1), ("nv48", 1)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_variable_coefficient_bdf_parity(zbm, which, jac_policy, precision):
+    """VODE's variable-coefficient BDF form (integrator 'bdf_variable') against the oracle's
+    form='variable', with either Jacobian policy: same statuses, results within the widened
+    bar (each side's own error from its run at rtol/100), and a step path of its own (the
+    fixed form takes different steps on the same zones)."""
+    zb, ctx = zbm
+    if which == "config2":
+        net_d, n, Tr, Td = W.config2_network(), 256, (1e3, 5e3), "uniform"
+    else:
+        k = {"nv22": 1, "nv48": 2}[which]
+        ns, R, seed = W.CONFIG3_NETS[k]
+        net_d, n, Tr, Td = W.random_network(ns, R, seed), [0, 128, 48][k], W.CONFIG3_T_RANGE, "loguniform"
+    st = W.random_zones(net_d, n, seed=781, T_range=Tr, T_dist=Td)
+    nv = net_d["n_species"] + net_d["thermal"]
+    ref = oracle.burn(net_d, st, 1.0, 1e-8, 1e-12, jac_policy=jac_policy, form="variable")
+    fine = oracle.burn(net_d, st, 1.0, 1e-10, 1e-14, jac_policy=jac_policy, form="variable",
+                       max_steps=10000000)
+    net = zb.Network(ctx, net_d)
+    out = []
+    for rt, at, ms, integ in ((1e-8, 1e-12, 0, "bdf_variable"), (1e-10, 1e-14, 10000000, "bdf_variable"),
+                              (1e-8, 1e-12, 0, "bdf")):
+        t = torch.tensor(st, device="cuda:0")
+        status, stats = zb.burn(ctx, net, t, 1.0, rt, at, precision=precision,
+                                jac_policy=jac_policy, max_steps=ms, integrator=integ)
+        zb.sync(ctx)
+        out.append((t.cpu().numpy(), status.cpu().numpy(), stats.cpu().numpy()))
+    check(f"{which} variable-coefficient {precision} policy {jac_policy}", out[0], (ref, fine),
+          1e-8, 1e-12, nv, out[1])
+    assert not np.array_equal(out[0][2][:, 0], out[2][2][:, 0])
+    net.close()
+
+
+@pytest.mark.parametrize("lanes", [1, 4])
+def test_variable_coefficient_bdf_robertson(zbm, lanes):
+    zb, ctx = zbm
+    c = W.config1(512)
+    ref = oracle.burn(c["net"], c["state"], c["dt"], 1e-8, 1e-12, scale=c["scale"], form="variable")
+    fine = oracle.burn(c["net"], c["state"], c["dt"], 1e-10, 1e-14, scale=c["scale"],
+                       form="variable", max_steps=10000000)
+    net = zb.Network(ctx, c["net"])
+    sc = torch.tensor(c["scale"], device="cuda:0")
+    out = []
+    for rt, at, ms in ((1e-8, 1e-12, 0), (1e-10, 1e-14, 10000000)):
+        t = torch.tensor(c["state"], device="cuda:0")
+        status, stats = zb.burn(ctx, net, t, c["dt"], rt, at, rate_scale=sc, lanes=lanes,
+                                max_steps=ms, integrator="bdf_variable")
+        zb.sync(ctx)
+        out.append((t.cpu().numpy(), status.cpu().numpy(), stats.cpu().numpy()))
+    check(f"robertson variable-coefficient L{lanes}", out[0], (ref, fine), 1e-8, 1e-12, 3, out[1])
+    net.close()
