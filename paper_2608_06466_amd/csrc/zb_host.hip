@@ -190,6 +190,14 @@ extern "C" zb_err zb_network_info(const zb_network *n, int32_t *n_var, int32_t *
 
 // ------------------------------------------------------------- kernel choice
 
+static size_t launch_lds(const KernelInfo *k, int max_nr)
+{
+    const int G = 64 / k->lanes;
+    const int rpl = (k->nvp + k->lanes - 1) / k->lanes;
+    const LdsLayout lay = lds_layout(k->nvp, k->lanes * rpl, max_nr, k->jac >= 3);
+    return (size_t)G * lay.total * sizeof(double);
+}
+
 static int default_lanes(int nv)
 {
     if (nv <= 4) return 1;
@@ -219,7 +227,17 @@ int zbh::lanes_for(zb_context *ctx, const zb_network *net, int prec, const zb_op
     std::lock_guard<std::mutex> lk(ctx->mu);
     for (auto &t : ctx->tuned)
         if (t.nv == net->dn.nv && t.nr == net->dn.nr && t.prec == prec) return t.lanes;
-    return default_lanes(net->dn.nv);
+    // The per-zone LDS area holds the reaction columns (5 doubles a reaction) once per zone of
+    // the wave, so a small network with many reactions needs wider groups: widen until two
+    // waves fit a CU.
+    const int steps[] = {1, 4, 8, 16, 32, 64};
+    const int L0 = default_lanes(net->dn.nv);
+    for (int L : steps) {
+        if (L < L0) continue;
+        const KernelInfo *k = find_kernel(net->dn.nv, L, prec == ZB_MIXED, 0);
+        if (k && launch_lds(k, net->dn.nr) <= 80 * 1024) return L;
+    }
+    return 64;
 }
 
 extern "C" zb_err zb_get_mapping(zb_context *ctx, const zb_network *net, int32_t precision, int32_t *lanes)
@@ -262,13 +280,6 @@ zb_err zbh::check_segment(zb_context *ctx, const zb_segment &s)
     return ZB_OK;
 }
 
-static size_t launch_lds(const KernelInfo *k, int max_nr)
-{
-    const int G = 64 / k->lanes;
-    const int rpl = (k->nvp + k->lanes - 1) / k->lanes;
-    const LdsLayout lay = lds_layout(k->nvp, k->lanes * rpl, max_nr, k->jac >= 3);
-    return (size_t)G * lay.total * sizeof(double);
-}
 
 int zbh::blocks_per_cu(const KernelInfo *k, int max_nr)
 {
@@ -641,7 +652,9 @@ extern "C" zb_err zb_autotune(zb_context *ctx, const zb_network *net, const doub
     zb_err res = ZB_OK;
     for (int li = 0, lanes = 1; lanes <= 64; ++li, lanes *= 2) {
         if (times_ms) times_ms[li] = -1.f;
-        if (!find_kernel(net->dn.nv, lanes, precision == ZB_MIXED, 0)) continue;
+        const KernelInfo *kk = find_kernel(net->dn.nv, lanes, precision == ZB_MIXED, 0);
+        if (!kk) continue;
+        if (launch_lds(kk, net->dn.nr) > 160 * 1024) continue;   // this mapping cannot launch
         zb_segment s = {net, work, zones, dt, rtol, atol, nullptr, st, nullptr};
         float ms = 0.f;
         for (int rep = 0; rep < 2; ++rep) {   // the first launch also loads the code object

@@ -6,6 +6,7 @@ import time
 import numpy as np
 import pytest
 
+import oracle
 from paper_2608_06466_amd import workloads as W
 
 torch = pytest.importorskip("torch")
@@ -200,3 +201,30 @@ def test_server_admission_waits_for_memory(zbm):
         srv.fetch(tickets[0])
     assert e3.value.code == zb.ENOTFOUND
     srv.close()
+
+
+def test_small_network_with_many_reactions_gets_a_mapping_that_fits(zbm):
+    """Three species and T with 80 reactions: one lane per zone would need more LDS than a
+    CU has (the reaction columns are kept once per zone of the wave), so the automatic
+    mapping takes wider groups; the burn runs and matches the oracle, and the autotuner
+    skips the mappings that cannot launch."""
+    zb, ctx = zbm[0], zbm[1]
+    net_d = W.random_network(3, 80, 911)
+    st = W.random_zones(net_d, 256, seed=912, T_range=(90.0, 300.0), T_dist="loguniform")
+    net = zb.Network(ctx, net_d)
+    lanes = zb.get_mapping(ctx, net, "fp64")
+    assert lanes > 1
+    t = torch.tensor(st, device="cuda:0")
+    status, stats = zb.burn(ctx, net, t, 1.0, 1e-8, 1e-12)
+    zb.sync(ctx)
+    ref = oracle.burn(net_d, st, 1.0, 1e-8, 1e-12)
+    out = t.cpu().numpy()
+    status = status.cpu().numpy()
+    assert np.array_equal(status, ref[1])
+    ok = ref[1] == 0
+    assert ok.sum() > 200
+    g = np.abs(out[ok, :4] - ref[0][ok, :4]) / np.maximum(np.abs(ref[0][ok, :4]), 1e-4)
+    assert g.max() < 1e-5   # accuracy proper is covered by the parity tests
+    best, times = zb.autotune(ctx, net, torch.tensor(st[:64], device="cuda:0"), 1.0, 1e-8, 1e-12)
+    assert best > 1 and times[0] < 0
+    net.close()
