@@ -9,9 +9,15 @@
 // from is a group-wide reduction with the same result in each lane.
 //
 // Exchange.  Group reductions use DPP (quad_perm, row_half_mirror,
-// row_mirror) and, across 16-lane rows, ds_bpermute.  The pivot row of the LU,
-// the state broadcast for the right-hand side, per-reaction rates and the
-// Jacobian assembly go through a per-group LDS area.
+// row_mirror) within 16-lane rows and v_permlane16_swap / v_permlane32_swap
+// across them.  The state broadcast for the right-hand side, per-reaction
+// rates, the Jacobian assembly and the LU pivot row (v_readlane for whole-wave
+// zones) go through a per-group LDS area.
+//
+// Methods (the kernel's fourth template parameter): the fixed-leading-
+// coefficient BDF with a Jacobian every step or the Jacobian/LU reuse, the
+// damped Runge-Kutta-Chebyshev method, and the variable-coefficient BDF with
+// either Jacobian policy.
 //
 // Scheduling.  The grid is persistent: every group pulls the next zone from
 // a device-wide atomic counter when its zone is done, so zones of very
@@ -302,27 +308,6 @@ __device__ __forceinline__ T gbcast(T v, bool owner)
     else return greduce<L>(owner ? v : T(0), OpAdd());
 }
 
-// Same, through a group LDS slot: one store by the owner, one load by everyone.
-template <int L, class T>
-__device__ __forceinline__ T gbcast_lds(T v, bool owner, double *slot)
-{
-    if constexpr (L == 1) return v;
-    if (owner) *slot = (double)v;
-    lds_fence();
-    T r = (T)*slot;
-    lds_fence();
-    return r;
-}
-
-#ifndef ZB_SOLVE_LDS
-#define ZB_SOLVE_LDS 0
-#endif
-template <int L, class T>
-__device__ __forceinline__ T gbcast_solve(T v, bool owner, double *slot)
-{
-    if constexpr (ZB_SOLVE_LDS) return gbcast_lds<L>(v, owner, slot);
-    else return gbcast<L>(v, owner);
-}
 
 // A group-uniform flag, stated as such for whole-wave groups (so code under it may keep
 // wave-uniform values in scalar registers).
@@ -897,7 +882,7 @@ __device__ __forceinline__ void lu_solve(const Ctx &c, const Zone<NVP, L, LT> &z
             LT cand = opq(bb[S]);
             if (ps[S] == k) { v = cand; own = true; }
         });
-        LT zk = gbcast_solve<L>(v, own, c.S + c.lay.xch);
+        LT zk = gbcast<L>(v, own);
         sfor<0, RPL>([&](auto S) {
             if (ps[S] > k) bb[S] = fma(-z.M[S][k], zk, bb[S]);
         });
@@ -913,7 +898,7 @@ __device__ __forceinline__ void lu_solve(const Ctx &c, const Zone<NVP, L, LT> &z
             LT cand = opq(bb[S]) * opq(z.dinv[S]);
             if (ps[S] == k) { v = cand; own = true; }
         });
-        LT xk = gbcast_solve<L>(v, own, c.S + c.lay.xch);
+        LT xk = gbcast<L>(v, own);
         sfor<0, RPL>([&](auto S) {
             if (ps[S] < k) bb[S] = fma(-z.M[S][k], xk, bb[S]);
         });

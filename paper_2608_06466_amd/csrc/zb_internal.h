@@ -58,7 +58,7 @@ struct BurnArgs {
 
 // Per-group LDS layout (in doubles).  Everything a zone group exchanges lives here.
 struct LdsLayout {
-    int xch, cnt, zs, ybuf, wbuf, prow, ks, rx, jbuf, vc, total;
+    int cnt, zs, ybuf, wbuf, prow, ks, rx, jbuf, vc, total;
 };
 
 // Variable-coefficient BDF slots (kernels of that form only): the accepted step sizes,
@@ -72,7 +72,6 @@ __host__ __device__ inline LdsLayout lds_layout(int nvp, int nvl, int nr, bool v
 {
     LdsLayout o;
     int p = 0;
-    o.xch = p;  p += 2;
     o.cnt = p;  p += 4;               // counters of a zone's first run while it is retried
     o.zs = p;   p += (QMAX + 1) * nvl;
     o.ybuf = p; p += nvp;
