@@ -36,9 +36,16 @@ FLAGS = [
 ]
 
 
+# The 16-, 24- and 32-row kernels run 1-3 % faster when the machine scheduler favours
+# instruction-level parallelism; the 48-row and small kernels do not (measured per class).
+MAX_ILP = {"zb_k16.hip", "zb_k16r.hip", "zb_k16n.hip", "zb_k24.hip", "zb_k24r.hip", "zb_k32.hip",
+           "zb_k32r.hip", "zb_kv_b.hip", "zb_kv_c.hip", "zb_kvr_b.hip", "zb_kvr_c.hip"}
+
+
 def _compile(src, verbose):
     obj = os.path.join(OBJ, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    extra = ["-mllvm", "-amdgpu-sched-strategy=max-ilp"] if src in MAX_ILP else []
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
