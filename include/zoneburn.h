@@ -62,7 +62,8 @@ typedef struct { int32_t nst, nfe, nje, nlu, nni, netf, ncf; } zb_zone_stats;
    w_r = k_r Y_a Y_b (k_r Y_a for one reactant).  dY_i/dt = sum_r nu_ir w_r and, when
    thermal, dT/dt = sum_r q_r w_r.  Arrays are HOST pointers, copied by zb_network_create. */
 typedef struct {
-    int32_t n_species;         /* 1 .. 64 (63 when thermal) */
+    int32_t n_species;         /* 1 .. 64 (63 when thermal); the burn kernels take
+                                  n_species + thermal <= 48 (ZB_EUNSUPPORTED beyond) */
     int32_t thermal;           /* 0: T is passed through unchanged; 1: T is integrated */
     int32_t n_reactions;       /* 0 .. 4096 */
     const int32_t *reactant;   /* [n_reactions][2] */
@@ -148,7 +149,9 @@ zb_err zb_network_info(const zb_network *net, int32_t *n_var, int32_t *n_reactio
    stream      hipStream_t (as void*), NULL for the null stream.  The call is asynchronous:
                argument errors return at once, everything else surfaces in zb_sync.
    ZB_EINVAL: zones < 0, dt not finite or <= 0, rtol <= 0, atol <= 0 (or not finite),
-   NULL state with zones > 0, or buffers of another device. */
+   NULL state with zones > 0, buffers of another device, or invalid opts.
+   ZB_EUNSUPPORTED: no kernel for the network size with this mapping and precision
+   (n_species + thermal > 48, or a forced mapping whose LDS needs more than a CU has). */
 zb_err zb_burn(zb_context *ctx, const zb_network *net, double *state, int64_t zones, double dt,
                double rtol, double atol, const double *rate_scale, const zb_opts *opts,
                int32_t *zone_status, zb_zone_stats *stats, void *stream);
