@@ -228,3 +228,38 @@ def test_small_network_with_many_reactions_gets_a_mapping_that_fits(zbm):
     best, times = zb.autotune(ctx, net, torch.tensor(st[:64], device="cuda:0"), 1.0, 1e-8, 1e-12)
     assert best > 1 and times[0] < 0
     net.close()
+
+
+def test_graph_and_server_take_the_method_options(zbm):
+    """The variable-coefficient form with the Jacobian reuse (VODE's configuration) through a
+    captured graph and through the server gives, bitwise, what zb_burn gives with the same
+    options."""
+    zb, ctx, nets_d, nets = zbm
+    opts = dict(precision="mixed", jac_policy=1, integrator="bdf_variable")
+    segs, host = make_segments(zb, nets_d, nets, [300, 120, 60, 24], seed=41)
+    init = [s["state"].clone() for s in segs]
+    ref = []
+    for k, (st, sc, dt) in enumerate(host):
+        t = torch.tensor(st, device="cuda:0")
+        s = None if sc is None else torch.tensor(sc, device="cuda:0")
+        status, stats = zb.burn(ctx, nets[k], t, dt, 1e-8, 1e-12, rate_scale=s, **opts)
+        zb.sync(ctx)
+        ref.append((t.cpu().numpy(), status.cpu().numpy(), stats.cpu().numpy()))
+    g = zb.Graph(ctx, segs, **opts)
+    for rep in range(2):
+        for s, i0 in zip(segs, init):
+            s["state"].copy_(i0)
+        torch.cuda.synchronize()
+        g.launch()
+        zb.sync(ctx)
+        for k, s in enumerate(segs):
+            assert np.array_equal(s["state"].cpu().numpy(), ref[k][0]), (rep, k)
+            assert np.array_equal(s["stats"].cpu().numpy(), ref[k][2]), (rep, k)
+    g.close()
+    srv = zb.Server(ctx, 64 << 20, slice_zones=50, **opts)
+    tickets = [srv.submit(nets[k], st, dt, 1e-8, 1e-12, sc) for k, (st, sc, dt) in enumerate(host)]
+    for k, t in enumerate(tickets):
+        assert srv.wait(t, timeout=120.0)
+        out, status, stats, info = srv.fetch(t)
+        assert np.array_equal(out, ref[k][0]) and np.array_equal(stats, ref[k][2]), k
+    srv.close()
