@@ -47,9 +47,9 @@ def step_flops(nv, nr, thermal, stats):
     return nje * per_att + nfe * per_rhs + nni * per_it
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "burn_kernel_16x16_nv14_2p20zones_hbm_traffic.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "burn_kernel_14x16_nv14_2p20zones_hbm_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2608_06466_amd", "csrc", f)
-                  for f in ("zb_burn_kernel.h", "zb_internal.h", "zb_k16.hip")] + [
+                  for f in ("zb_burn_kernel.h", "zb_internal.h", "zb_k14.hip")] + [
                   os.path.join(ROOT, "paper_2608_06466_amd", "build.py")]   # the compile flags
 
 

@@ -9,6 +9,12 @@ namespace zb {
 
 int kernels_04(const KernelInfo **out);
 int kernels_16(const KernelInfo **out);
+int kernels_14(const KernelInfo **out);
+int kernels_14r(const KernelInfo **out);
+int kernels_14v(const KernelInfo **out);
+int kernels_14vr(const KernelInfo **out);
+int kernels_22(const KernelInfo **out);
+int kernels_22r(const KernelInfo **out);
 int kernels_16n(const KernelInfo **out);
 int kernels_24(const KernelInfo **out);
 int kernels_32(const KernelInfo **out);
@@ -55,6 +61,12 @@ int kernel_table(const KernelInfo **out)
         };
         add(kernels_04);
         add(kernels_16);
+        add(kernels_14);
+        add(kernels_14r);
+        add(kernels_14v);
+        add(kernels_14vr);
+        add(kernels_22);
+        add(kernels_22r);
         add(kernels_16n);
         add(kernels_24);
         add(kernels_32);
