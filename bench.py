@@ -324,7 +324,8 @@ def robertson(args):
 
 def batched(args):
     """Four networks (nv 3, 14, 22, 48; 4:2:1:1 of 2^21 zones) in one zb_burn_batch call, FP64
-    (config 3) and with the FP32 LU (config 4), each against the oracle on a stratified sample."""
+    (config 3) and with the FP32 LU (config 4), each against the oracle on a stratified sample;
+    the FP32 run again with the blocked matrix-core LU (lu='mfma': the 48-variable class)."""
     import torch
     import oracle
     from paper_2608_06466_amd import workloads as W
@@ -342,7 +343,8 @@ def batched(args):
                  rate_scale=scales[k], status=status[k], stats=stats[k]) for k, s in enumerate(segs_h)]
     stream = torch.cuda.current_stream()
     res = {}
-    for prec in ("fp64", "mixed"):
+    for key, prec, lu in (("fp64", "fp64", "valu"), ("mixed", "mixed", "valu"),
+                          ("mixed_mfma", "mixed", "mfma")):
         ts = []
         for it in range(args.warmup + args.steps):
             for w, i0 in zip(work, init):
@@ -351,12 +353,12 @@ def batched(args):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             t0 = time.perf_counter()
             e0.record(stream)
-            zb.burn_batch(ctx, segs, precision=prec)
+            zb.burn_batch(ctx, segs, precision=prec, lu=lu)
             e1.record(stream)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             nf = zb.sync(ctx)
-            print(f"[bench] batched {prec} step {it}: {(t1 - t0) * 1e3:.1f} ms, failed zones {nf}",
+            print(f"[bench] batched {key} step {it}: {(t1 - t0) * 1e3:.1f} ms, failed zones {nf}",
                   file=sys.stderr, flush=True)
             if it >= args.warmup:
                 ts.append((t1 - t0, e0.elapsed_time(e1)))
@@ -365,7 +367,7 @@ def batched(args):
              "stats": [s.cpu().numpy() for s in stats]}
         r["ok"] = int(sum((s == 0).sum() for s in r["status"]))
         r["flops"] = float(sum(step_flops(n.nv, n.nr, n.thermal, st) for n, st in zip(nets, r["stats"])))
-        res[prec] = r
+        res[key] = r
     per_class = []
     for k, s in enumerate(segs_h):
         st = res["fp64"]["stats"][k][:, 0]
@@ -388,11 +390,17 @@ def batched(args):
                           "roofline": roof(f)}
     line["roofline"] = roof(m)
     line["mixed_over_fp64"] = round((m["ok"] / m["wall_s"]) / (f["ok"] / f["wall_s"]), 3)
+    b = res["mixed_mfma"]
+    line["mfma_lu"] = {"value": round(b["ok"] / b["wall_s"], 1), "ms_per_step": round(b["wall_s"] * 1e3, 2),
+                       "over_valu_lu": round((b["ok"] / b["wall_s"]) / (m["ok"] / m["wall_s"]), 3),
+                       "note": "mixed precision with lu='mfma': the 48-variable class factors with the "
+                               "blocked LU (trailing updates as FP32 MFMA products), the others keep "
+                               "the vector-unit LU"}
     if not args.no_cpu:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         threads = max(1, min(threads, os.cpu_count() or 1))
         rng = np.random.default_rng(4321)
-        acc = {"fp64": [], "mixed": []}
+        acc = {"fp64": [], "mixed": [], "mixed_mfma": []}
         cpu_time_per_zone = []
         for k, s in enumerate(segs_h):
             nz = s["state"].shape[0]
@@ -402,7 +410,7 @@ def batched(args):
             ref, rst, _ = oracle.burn(s["net"], s["state"][idx], s["dt"], s["rtol"], s["atol"],
                                       None if s["scale"] is None else s["scale"][idx], nthreads=threads)
             cpu_time_per_zone.append((time.perf_counter() - t0) / n)
-            for prec in ("fp64", "mixed"):
+            for prec in ("fp64", "mixed", "mixed_mfma"):
                 out = res[prec]["out"][k][idx]
                 ok = (rst == 0) & (res[prec]["status"][k][idx] == 0)
                 g = _gated(out[ok], ref[ok], nets[k].nv, s["rtol"], s["atol"])

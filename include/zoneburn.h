@@ -80,6 +80,7 @@ enum { ZB_MAP_AUTO = 0 };                          /* zb_opts.mapping: else lane
 enum { ZB_JAC_EVERY_STEP = 0, ZB_JAC_REUSE = 1 };  /* zb_opts.jac_policy */
 enum { ZB_BDF = 0, ZB_RKC = 1, ZB_BDF_VARIABLE = 2 };   /* zb_opts.integrator */
 enum { ZB_RETRY_JAC_ANALYTIC = 0, ZB_RETRY_JAC_FD = 1 };   /* zb_opts.retry_jac */
+enum { ZB_LU_VALU = 0, ZB_LU_MFMA = 1 };           /* zb_opts.lu */
 
 typedef struct {
     int32_t max_steps;   /* accepted steps per zone before ZB_ZONE_MAXSTEPS (<= 0: 100000) */
@@ -127,6 +128,15 @@ typedef struct {
                             d_j = 2^-26 max(|y_j|, atol + rtol |y_j|) taken as (y_j + d_j) - y_j;
                             each one adds nv to the zone's nfe.  BDF only: ZB_EINVAL with ZB_RKC
                             when retry is on. */
+    int32_t lu;          /* factorisation of the iteration matrix (the paper, Solvers: a dense LU).
+                            ZB_LU_VALU (0): right-looking LU with partial pivoting on the vector
+                            units, the default.  ZB_LU_MFMA (1): the same pivoting in 16-column
+                            panels, each panel's update of the columns right of it done as one
+                            FP32 product on the matrix cores (v_mfma_f32_32x32x2f32,
+                            v_mfma_f32_16x16x4f32).  It needs ZB_MIXED, ZB_JAC_EVERY_STEP and a
+                            BDF integrator (else ZB_EINVAL).  It applies to networks of 33 to 48
+                            variables on 64 lanes per zone; other mappings keep ZB_LU_VALU.  On
+                            MI355X it is slower than ZB_LU_VALU at these sizes. */
 } zb_opts;
 
 /* Create a context on HIP device `device` (allocates a small device workspace). */

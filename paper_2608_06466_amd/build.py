@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libzoneburn.so")
 SOURCES = [
     # the 48-row kernels compile slowest: first, so the parallel build starts them early
     "zb_k48d.hip", "zb_k48f.hip", "zb_k48dr.hip", "zb_k48fr.hip",
-    "zb_kv_d.hip", "zb_kv_e.hip", "zb_kvr_d.hip", "zb_kvr_e.hip",
+    "zb_kv_d.hip", "zb_kv_e.hip", "zb_kvr_d.hip", "zb_kvr_e.hip", "zb_k48b.hip",
     "zb_k16.hip", "zb_k14.hip", "zb_k14r.hip", "zb_k14v.hip", "zb_k14vr.hip", "zb_k22.hip",
     "zb_k22r.hip", "zb_k16r.hip", "zb_k16n.hip", "zb_k24.hip", "zb_k24r.hip", "zb_k32.hip",
     "zb_k32r.hip", "zb_k04.hip", "zb_k04r.hip", "zb_kc.hip",
@@ -46,7 +46,8 @@ SCHED = {
                               "zb_k24r.hip", "zb_k32.hip", "zb_k32r.hip", "zb_kv_b.hip",
                               "zb_kv_c.hip", "zb_kvr_b.hip", "zb_kvr_c.hip")},
     **{f: "iterative-ilp" for f in ("zb_k48d.hip", "zb_k48f.hip", "zb_k48dr.hip", "zb_k48fr.hip",
-                                    "zb_kv_d.hip", "zb_kv_e.hip", "zb_kvr_d.hip", "zb_kvr_e.hip")},
+                                    "zb_kv_d.hip", "zb_kv_e.hip", "zb_kvr_d.hip", "zb_kvr_e.hip",
+                                    "zb_k48b.hip")},
 }
 
 

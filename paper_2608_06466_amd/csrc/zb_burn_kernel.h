@@ -327,10 +327,6 @@ __device__ __forceinline__ bool gany(bool b)
 // Integration methods (the compile-time fourth parameter of the burn kernel): the
 // fixed-leading-coefficient BDF with a Jacobian every step or reused, RKC, and the
 // variable-coefficient BDF with either Jacobian policy.
-enum { METHOD_BDF = 0, METHOD_BDF_REUSE = 1, METHOD_RKC = 2, METHOD_BDF_VC = 3,
-       METHOD_BDF_VC_REUSE = 4 };
-constexpr bool method_vc(int m) { return m == METHOD_BDF_VC || m == METHOD_BDF_VC_REUSE; }
-constexpr int method_jac(int m) { return (m == METHOD_BDF_REUSE || m == METHOD_BDF_VC_REUSE) ? 1 : 0; }
 constexpr int RKC_SMAX = 250;
 
 // --------------------------------------------------------- BDF coefficients
@@ -445,10 +441,15 @@ struct Ctx {
     double rtol, atol, dt;
     int64_t zone;
     int jac_policy;
+    bool lu_blocked;         // the blocked matrix-core LU (48-row FP32 kernels)
 };
 
 template <int NVP, int L>
 __device__ __forceinline__ int row_of(const Ctx &c, int s) { return c.gl + L * s; }
+
+// Element type of the Jacobian rows in LDS.
+template <int NVP, class LT>
+using JacT = std::conditional_t<jac_f32(NVP, sizeof(LT) == 4), float, double>;
 
 // Weighted RMS norm over the nv integrated components.
 template <int NVP, int L, class LT>
@@ -481,7 +482,8 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
     double *ybuf = c.S + c.lay.ybuf;
     double *ks = c.S + c.lay.ks;
     double *rx = c.S + c.lay.rx;
-    double *jb = c.S + c.lay.jbuf;
+    using JT = JacT<NVP, LT>;
+    JT *jb = (JT *)(c.S + c.lay.jbuf);
 
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
@@ -494,7 +496,7 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
         // clear the Jacobian rows this lane owns (the T row is fully overwritten)
         sfor<0, RPL>([&](auto S) {
             int i = row_of<NVP, L>(c, S);
-            if (i < N.ns) sfor<0, NVP>([&](auto J) { jb[i * JS + J] = 0.0; });
+            if (i < N.ns) sfor<0, NVP>([&](auto J) { jb[i * JS + J] = JT(0); });
         });
     }
     lds_fence();
@@ -556,13 +558,13 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
             // in list order; each entry carries the reactant columns it feeds
             const int4 *lst = (const int4 *)(N.inv + i * N.inv_len);
             double jit = 0.0;
-            double *jrow = jb + i * JS;
+            JT *jrow = jb + i * JS;
             auto jadd = [&](int y, double nu, double da, double db) {
                 const int a = y & 0xff, b = (y >> 8) - 1;
-                __hip_atomic_fetch_add(jrow + a, nu * da, __ATOMIC_RELAXED,
+                __hip_atomic_fetch_add(jrow + a, (JT)(nu * da), __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
                 if (b >= 0)
-                    __hip_atomic_fetch_add(jrow + b, nu * db, __ATOMIC_RELAXED,
+                    __hip_atomic_fetch_add(jrow + b, (JT)(nu * db), __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
             };
             // A pair of entries: the second is taken under a predicate (a padding entry
@@ -600,7 +602,7 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
                 if (en.z < 0) break;
             }
             if (WANTJ && N.thermal) {
-                jrow[N.ns] = jit;
+                jrow[N.ns] = (JT)jit;
                 // T row: sum over the reactions that consume species i of q_r dw_r/dY_i
                 const int4 *rl = N.rea + i * N.rea_len;
                 double v = 0.0;
@@ -631,11 +633,11 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
                     if (!has1) break;
                     tent(e1, a1, b1);
                 }
-                jb[N.ns * JS + i] = v;
+                jb[N.ns * JS + i] = (JT)v;
             }
         } else if (N.thermal && i == N.ns) {
             fi = fT;
-            if (WANTJ) jb[N.ns * JS + N.ns] = JTT;
+            if (WANTJ) jb[N.ns * JS + N.ns] = (JT)JTT;
         }
         fo[s] = fi + z.src[s];
     }
@@ -654,7 +656,8 @@ __device__ __forceinline__ void fd_jacobian(const Ctx &c, Zone<NVP, L, LT> &z,
 {
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
     constexpr int JS = NVP + 1;
-    double *jb = c.S + c.lay.jbuf;
+    using JT = JacT<NVP, LT>;
+    JT *jb = (JT *)(c.S + c.lay.jbuf);
     eval<false>(c, z, yv, fo);
     const int nv = c.net.nv;
     for (int j = 0; j < nv; ++j) {
@@ -677,7 +680,7 @@ __device__ __forceinline__ void fd_jacobian(const Ctx &c, Zone<NVP, L, LT> &z,
 #pragma unroll
         for (int s = 0; s < RPL; ++s) {
             const int i = row_of<NVP, L>(c, s);
-            if (i < nv) jb[i * JS + j] = (fp[s] - fo[s]) / dj;
+            if (i < nv) jb[i * JS + j] = (JT)((fp[s] - fo[s]) / dj);
         }
         z.nfe++;
     }
@@ -693,7 +696,7 @@ __device__ __forceinline__ void form_M(const Ctx &c, Zone<NVP, L, LT> &z, double
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
     constexpr int JS = NVP + 1;
     const DevNet &N = c.net;
-    const double *jb = c.S + c.lay.jbuf;
+    const JacT<NVP, LT> *jb = (const JacT<NVP, LT> *)(c.S + c.lay.jbuf);
     lds_fence();
     constexpr bool MIXED = sizeof(LT) == 4;
     const double *wb = c.S + c.lay.wbuf;
@@ -703,7 +706,7 @@ __device__ __forceinline__ void form_M(const Ctx &c, Zone<NVP, L, LT> &z, double
         double mrow[NVP];
         if (i < N.nv) {
             sfor<0, NVP>([&](auto J) {
-                double m = (J == i ? 1.0 : 0.0) - gamma * jb[i * JS + J];
+                double m = (J == i ? 1.0 : 0.0) - gamma * (double)jb[i * JS + J];
                 if (J >= N.nv) m = (J == i) ? 1.0 : 0.0;
                 if (MIXED) {
                     m *= wb[J];
@@ -731,9 +734,186 @@ __device__ __forceinline__ void form_M(const Ctx &c, Zone<NVP, L, LT> &z, double
 
 // --------------------------------------------------------------- LU / solve
 
+typedef float zb_v16f __attribute__((ext_vector_type(16)));
+typedef float zb_v4f __attribute__((ext_vector_type(4)));
+
+// The LU of the whole-wave 48-row FP32 kernels, blocked for the matrix cores, under the
+// every-step Jacobian policy.  Three panels of 16 columns.  A panel is factored as in the
+// unblocked code (pivot search, multipliers, rank-1 updates), the updates kept to the
+// panel's own columns.  The columns right of it then take the panel's updates at once:
+//  - the panel's pivot rows are reduced by the panel's unit lower triangle (a 16-step
+//    triangular solve, one column per lane), giving U, their final parts there;
+//  - the rows still unpivoted (32 after the first panel, 16 after the second, in lane
+//    order) lose Lp U, Lp their multipliers of the panel: one product on the matrix cores,
+//    v_mfma_f32_32x32x2f32 for 32 x 32 x 16, v_mfma_f32_16x16x4f32 for 16 x 16 x 16.
+// Operands and product change lane layout through the Jacobian's LDS area, which is unused
+// from the formation of M to the next Jacobian.  Rows of M past nv are identity rows and
+// come last in lane order, so every row with a nonzero update fits the product.
+template <int NVP, int L, class LT>
+__device__ __forceinline__ void lu_factor_blocked(const Ctx &c, Zone<NVP, L, LT> &z)
+{
+    static_assert(NVP == 48 && L == 64 && sizeof(LT) == 4, "whole-wave 48-row FP32 LU");
+    constexpr int PB = 16;                            // panel width
+    constexpr int SU = 36, SA = 20, SL = 20, SD = 40; // LDS row strides (floats)
+    float *const UT = (float *)(c.S + c.lay.jbuf);    // 16 x SU: pivot rows right of the panel
+    float *const AT = UT + PB * SU;                    // 32 x SA: multipliers of unpivoted rows
+    float *const LW = AT + 32 * SA;                    // 16 x SL: the panel's lower triangle
+    float *const DT = AT;                              // 32 x SD: the product (AT, LW read by then)
+    const int nv = own_copy(c.net.nv);
+    const int lane = c.gl;
+    z.pstep[0] = 127;
+    z.pivlane = lane;
+    sfor<0, NVP / PB>([&](auto P) {
+        constexpr int c0 = P * PB;
+        sfor<0, PB>([&](auto KK) {
+            constexpr int k = c0 + KK;
+            if (k >= nv) return;
+            LT bv = LT(-1);
+            int bi = 1 << 20;
+            {
+                const LT a = fabs(z.M[0][k]);
+                if (z.pstep[0] > k && lane < nv && a > bv) {
+                    bv = a;
+                    bi = lane;
+                }
+            }
+            const LT gm = greduce<L>(bv, OpMax());
+            const unsigned long long msk = __ballot(bv == gm && bi < (1 << 20));
+            const int p = msk ? (int)__builtin_ctzll(msk) : (1 << 20);
+            const LT rinv = recip(lane_read(z.M[0][k], p));
+            if (lane == p) {
+                z.pstep[0] = k;
+                z.dinv[0] = rinv;
+            }
+            const bool act = z.pstep[0] > k;
+            const LT l = act ? z.M[0][k] * rinv : LT(0);
+            if (act) z.M[0][k] = l;
+            int pp = p;
+            sfor<k + 1, c0 + PB>([&](auto J) {
+                if constexpr (J % 8 == 0) pp = after_s(pp, z.M[0][J - 1]);
+                z.M[0][J] = fma(-l, lane_read(z.M[0][J], pp), z.M[0][J]);
+            });
+            if (lane == k) z.pivlane = p;
+        });
+        if constexpr (c0 + PB < NVP) {
+            constexpr int NT = NVP - c0 - PB;         // columns right of the panel = rows left
+            const bool unp = lane < NVP && z.pstep[0] >= c0 + PB;
+            const unsigned long long um = __ballot(unp);
+            const int ci = (int)__builtin_amdgcn_mbcnt_hi(
+                (unsigned)(um >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)um, 0u));
+            const int kk = z.pstep[0] - c0;
+            const bool piv = lane < NVP && kk >= 0 && kk < PB;
+            const bool inA = unp && ci < NT;
+            lds_fence();
+            if (inA) {
+                float a[PB];
+                sfor<0, PB>([&](auto KK) { a[KK] = (c0 + KK < nv) ? z.M[0][c0 + KK] : 0.0f; });
+                float4 *ar = (float4 *)(AT + ci * SA);
+                if constexpr (P == 0) {   // [k % 2][k / 2]: the 32x32x2 A layout
+                    ar[0] = make_float4(a[0], a[2], a[4], a[6]);
+                    ar[1] = make_float4(a[8], a[10], a[12], a[14]);
+                    ar[2] = make_float4(a[1], a[3], a[5], a[7]);
+                    ar[3] = make_float4(a[9], a[11], a[13], a[15]);
+                } else {                  // [k % 4][k / 4]: the 16x16x4 A layout
+                    ar[0] = make_float4(a[0], a[4], a[8], a[12]);
+                    ar[1] = make_float4(a[1], a[5], a[9], a[13]);
+                    ar[2] = make_float4(a[2], a[6], a[10], a[14]);
+                    ar[3] = make_float4(a[3], a[7], a[11], a[15]);
+                }
+            }
+            if (piv) {
+                float4 *lr = (float4 *)(LW + kk * SL);
+                sfor<0, PB / 4>([&](auto Q) {
+                    constexpr int j = c0 + 4 * Q;
+                    lr[Q] = make_float4(z.M[0][j], z.M[0][j + 1], z.M[0][j + 2], z.M[0][j + 3]);
+                });
+                float4 *ur = (float4 *)(UT + kk * SU);
+                sfor<0, NT / 4>([&](auto Q) {
+                    constexpr int j = c0 + PB + 4 * Q;
+                    ur[Q] = make_float4(z.M[0][j], z.M[0][j + 1], z.M[0][j + 2], z.M[0][j + 3]);
+                });
+            }
+            lds_fence();
+            // U by columns, written back in place
+            if (lane < NT) {
+                float u[PB];
+                sfor<0, PB>([&](auto KK) { u[KK] = (c0 + KK < nv) ? UT[KK * SU + lane] : 0.0f; });
+                sfor<1, PB>([&](auto KK) {
+                    constexpr int kq = KK;
+                    if (c0 + kq >= nv) return;
+                    const float *lr = LW + kq * SL;   // same address in every lane
+                    sfor<0, kq>([&](auto JJ) { u[kq] = fma(-lr[JJ], u[JJ], u[kq]); });
+                });
+                sfor<0, PB>([&](auto KK) { UT[KK * SU + lane] = u[KK]; });
+            }
+            lds_fence();
+            // Lp U for the unpivoted rows
+            if constexpr (P == 0) {
+                const int n = lane & 31, h = lane >> 5;
+                const float4 x0 = *(const float4 *)(AT + n * SA + 8 * h);
+                const float4 x1 = *(const float4 *)(AT + n * SA + 8 * h + 4);
+                const float av[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+                zb_v16f acc = {};
+                sfor<0, PB / 2>([&](auto KB) {
+                    constexpr int kb = KB;
+                    const int r = 2 * kb + h;
+                    const float b = (c0 + r < nv) ? UT[r * SU + n] : 0.0f;
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[kb], b, acc, 0, 0, 0);
+                });
+                lds_fence();
+                sfor<0, 16>([&](auto V) {
+                    constexpr int v = V;
+                    DT[(8 * (v / 4) + 4 * h + (v % 4)) * SD + n] = acc[v];
+                });
+            } else {
+                const int m = lane & 15, g = lane >> 4;
+                const float4 x = *(const float4 *)(AT + m * SA + 4 * g);
+                const float av[4] = {x.x, x.y, x.z, x.w};
+                zb_v4f acc = {};
+                sfor<0, PB / 4>([&](auto KB) {
+                    constexpr int kb = KB;
+                    const int r = 4 * kb + g;
+                    const float b = (c0 + r < nv) ? UT[r * SU + m] : 0.0f;
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[kb], b, acc, 0, 0, 0);
+                });
+                lds_fence();
+                sfor<0, 4>([&](auto V) {
+                    constexpr int v = V;
+                    DT[(4 * g + v) * SD + m] = acc[v];
+                });
+            }
+            lds_fence();
+            // pivot rows take U, unpivoted rows lose Lp U
+            if (inA || piv) {
+                const float *src = piv ? UT + kk * SU : DT + ci * SD;
+                sfor<0, NT / 4>([&](auto Q) {
+                    constexpr int j = c0 + PB + 4 * Q;
+                    const float4 d = *(const float4 *)(src + 4 * Q);
+                    z.M[0][j] = piv ? d.x : z.M[0][j] - d.x;
+                    z.M[0][j + 1] = piv ? d.y : z.M[0][j + 1] - d.y;
+                    z.M[0][j + 2] = piv ? d.z : z.M[0][j + 2] - d.z;
+                    z.M[0][j + 3] = piv ? d.w : z.M[0][j + 3] - d.w;
+                });
+            }
+            lds_fence();
+        }
+    });
+    // pivot row k to lane k, as in lu_factor
+    const int src = z.pivlane;
+    sfor<0, NVP>([&](auto J) { z.M[0][J] = gather(z.M[0][J], src); });
+    z.dinv[0] = gather(z.dinv[0], src);
+    z.rs[0] = gather(z.rs[0], src);
+}
+
 template <int NVP, int L, class LT>
 __device__ __forceinline__ void lu_factor(const Ctx &c, Zone<NVP, L, LT> &z)
 {
+    if constexpr (NVP == 48 && L == 64 && sizeof(LT) == 4) {
+        if (c.lu_blocked) {
+            lu_factor_blocked(c, z);
+            return;
+        }
+    }
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
     LT *prow = (LT *)(c.S + c.lay.prow);
     const int nv = own_copy(c.net.nv);
@@ -1395,13 +1575,13 @@ __device__ __forceinline__ int zone_attempt_rkc(const Ctx &c, Zone<NVP, L, LT> &
         z.nje++;
     }
     lds_fence();
-    const double *jb = c.S + c.lay.jbuf;
+    const JacT<NVP, LT> *jb = (const JacT<NVP, LT> *)(c.S + c.lay.jbuf);
     double rs = 0.0;
     sfor<0, RPL>([&](auto S) {
         const int i = row_of<NVP, L>(c, S);
         if (i < N.nv) {
             double r = 0.0;
-            for (int j = 0; j < N.nv; ++j) r += fabs(jb[i * JS + j]);
+            for (int j = 0; j < N.nv; ++j) r += fabs((double)jb[i * JS + j]);
             rs = fmax(rs, r);
         }
     });
@@ -1551,7 +1731,7 @@ __device__ __forceinline__ T uniform(T v)
 
 // Segment data for the wave (the wave works on one segment at a time, so it is uniform).
 __device__ __forceinline__ void load_segment(Ctx &c, const BurnArgs &A, int seg, int nvp, int nvl,
-                                             bool vc)
+                                             bool vc, bool jf32)
 {
     // seg is wave-uniform: scalar loads from the kernel-argument segment
     const BurnArgs *pa = (const BurnArgs *)__builtin_amdgcn_kernarg_segment_ptr();
@@ -1574,7 +1754,7 @@ __device__ __forceinline__ void load_segment(Ctx &c, const BurnArgs &A, int seg,
     c.rtol = uniform(S.rtol);
     c.atol = uniform(S.atol);
     c.dt = uniform(S.dt);
-    c.lay = lds_layout(nvp, nvl, A.max_nr, vc);
+    c.lay = lds_layout(nvp, nvl, A.max_nr, vc, jf32);
 }
 
 // Persistent kernel.  Each wave works through the segments in order; within a
@@ -1607,10 +1787,11 @@ void burn_kernel(BurnArgs A)
     const int g = lane / L;
     Zone<NVP, L, LT> z;
     int seg = 0;
-    c.jac_policy = JP == METHOD_RKC ? METHOD_RKC : method_jac(JP);   // a constant: each
+    c.jac_policy = JP == METHOD_RKC ? METHOD_RKC : method_jac(JP);
+    c.lu_blocked = method_blocked_lu(JP);   // a constant: each
                          // method is its own kernel (the reuse keeps the
                          // factors live across steps, which costs registers)
-    load_segment(c, A, seg, NVP, L * RPL, method_vc(JP));
+    load_segment(c, A, seg, NVP, L * RPL, method_vc(JP), jac_f32(NVP, sizeof(LT) == 4));
     c.S = smem + g * c.lay.total;
     int64_t zones = uniform(A.seg[0].zones);
     bool need = true, dry = false;
@@ -1637,7 +1818,7 @@ void burn_kernel(BurnArgs A)
         }
         if (__ballot(!dry) == 0) {
             if (++seg >= A.nseg) break;
-            load_segment(c, A, seg, NVP, L * RPL, method_vc(JP));
+            load_segment(c, A, seg, NVP, L * RPL, method_vc(JP), jac_f32(NVP, sizeof(LT) == 4));
             c.S = smem + g * c.lay.total;
             {
                 const BurnArgs *pa = (const BurnArgs *)__builtin_amdgcn_kernarg_segment_ptr();
@@ -1681,5 +1862,7 @@ void burn_kernel(BurnArgs A)
 #define ZB_KC(NVP, L) {NVP, L, 0, 2, (const void *)&burn_kernel<NVP, L, double, 2>}
 #define ZB_KV(NVP, L, LT, MIX) {NVP, L, MIX, 3, (const void *)&burn_kernel<NVP, L, LT, 3>}
 #define ZB_KVR(NVP, L, LT, MIX) {NVP, L, MIX, 4, (const void *)&burn_kernel<NVP, L, LT, 4>}
+#define ZB_KB(NVP, L) {NVP, L, 1, 5, (const void *)&burn_kernel<NVP, L, float, 5>}
+#define ZB_KVB(NVP, L) {NVP, L, 1, 6, (const void *)&burn_kernel<NVP, L, float, 6>}
 
 }  // namespace zb

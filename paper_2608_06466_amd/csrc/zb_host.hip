@@ -194,7 +194,8 @@ static size_t launch_lds(const KernelInfo *k, int max_nr)
 {
     const int G = 64 / k->lanes;
     const int rpl = (k->nvp + k->lanes - 1) / k->lanes;
-    const LdsLayout lay = lds_layout(k->nvp, k->lanes * rpl, max_nr, k->jac >= 3);
+    const LdsLayout lay = lds_layout(k->nvp, k->lanes * rpl, max_nr, method_vc(k->jac),
+                                     jac_f32(k->nvp, k->mixed != 0));
     return (size_t)G * lay.total * sizeof(double);
 }
 
@@ -208,6 +209,16 @@ static int default_lanes(int nv)
 }
 
 // Smallest kernel with nvp >= nv for the given lanes and precision.
+// The kernel of a method; the blocked-LU methods exist for the 48-row whole-wave kernels
+// only, and other mappings take the same method with the vector-unit LU.
+const KernelInfo *zbh::kernel_for(int nv, int lanes, int mixed, int method)
+{
+    const KernelInfo *k = find_kernel(nv, lanes, mixed, method);
+    if (!k && method_blocked_lu(method))
+        k = find_kernel(nv, lanes, mixed, method_vc(method) ? METHOD_BDF_VC : METHOD_BDF);
+    return k;
+}
+
 const KernelInfo *zbh::find_kernel(int nv, int lanes, int mixed, int jac)
 {
     const KernelInfo *tab;
@@ -259,6 +270,18 @@ static bool valid_ptr(const void *p, int device)
     }
     if (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) return a.device == device;
     return false;
+}
+
+zb_err zbh::check_lu(const zb_opts *o, int prec)
+{
+    if (!o || o->lu == ZB_LU_VALU) return ZB_OK;
+    if (o->lu != ZB_LU_MFMA) return fail(ZB_EINVAL, "lu %d", o->lu);
+    if (prec != ZB_MIXED) return fail(ZB_EINVAL, "the matrix-core LU is FP32: use ZB_MIXED");
+    if (o->integrator == ZB_RKC) return fail(ZB_EINVAL, "the RKC integrator has no LU");
+    if (o->jac_policy != ZB_JAC_EVERY_STEP)
+        return fail(ZB_EINVAL, "the matrix-core LU takes the Jacobian every step (its LDS staging "
+                               "area holds the Jacobian otherwise)");
+    return ZB_OK;
 }
 
 zb_err zbh::check_segment(zb_context *ctx, const zb_segment &s)
@@ -410,6 +433,10 @@ static zb_err plan_groups(zb_context *ctx, const zb_segment *segs, int n, const 
         return fail(ZB_EINVAL, "retry_jac %d", opts->retry_jac);
     if (opts && opts->retry && rkc && opts->retry_jac == ZB_RETRY_JAC_FD)
         return fail(ZB_EINVAL, "the finite-difference retry Jacobian is a BDF option");
+    {
+        const zb_err e = check_lu(opts, prec);
+        if (e != ZB_OK) return e;
+    }
     const int jac = method_of(opts);
     for (int i = 0; i < n; ++i) {
         zb_err e = check_segment(ctx, segs[i]);
@@ -419,7 +446,7 @@ static zb_err plan_groups(zb_context *ctx, const zb_segment *segs, int n, const 
     for (int i = 0; i < n; ++i) {
         if (segs[i].zones == 0) continue;
         int lanes = force_lanes ? force_lanes : lanes_for(ctx, segs[i].net, prec, opts);
-        const KernelInfo *k = find_kernel(segs[i].net->dn.nv, lanes, prec == ZB_MIXED, jac);
+        const KernelInfo *k = kernel_for(segs[i].net->dn.nv, lanes, prec == ZB_MIXED, jac);
         if (!k)
             return fail(ZB_EUNSUPPORTED, "no kernel for nv=%d with %d lanes per zone (%s)",
                         segs[i].net->dn.nv, lanes, prec == ZB_MIXED ? "mixed" : "fp64");

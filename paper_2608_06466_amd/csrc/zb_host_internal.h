@@ -49,15 +49,19 @@ struct Workspace {
 };
 
 const zb::KernelInfo *find_kernel(int nv, int lanes, int mixed, int jac);
+const zb::KernelInfo *kernel_for(int nv, int lanes, int mixed, int method);
 
-// Kernel method of validated options: 0/1 fixed-coefficient BDF (Jacobian every step /
-// reused), 2 RKC, 3/4 variable-coefficient BDF (every step / reused).
+// Kernel method (METHOD_*) of validated options.
 inline int method_of(const zb_opts *o)
 {
-    if (!o) return 0;
-    if (o->integrator == ZB_RKC) return 2;
-    return o->jac_policy + (o->integrator == ZB_BDF_VARIABLE ? 3 : 0);
+    if (!o) return zb::METHOD_BDF;
+    if (o->integrator == ZB_RKC) return zb::METHOD_RKC;
+    const bool vc = o->integrator == ZB_BDF_VARIABLE;
+    if (o->lu == ZB_LU_MFMA) return vc ? zb::METHOD_BDF_VC_BLU : zb::METHOD_BDF_BLU;
+    return o->jac_policy + (vc ? zb::METHOD_BDF_VC : zb::METHOD_BDF);
 }
+// zb_opts.lu against the rest of the options (precision prec).
+zb_err check_lu(const zb_opts *o, int prec);
 int lanes_for(zb_context *ctx, const zb_network *net, int prec, const zb_opts *o);
 zb_err check_segment(zb_context *ctx, const zb_segment &s);
 // Validates the segments and launches them (one persistent launch per kernel

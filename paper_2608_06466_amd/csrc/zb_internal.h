@@ -56,6 +56,24 @@ struct BurnArgs {
     unsigned long long *nfail;     // zones that ended with a non-OK status
 };
 
+// Kernel methods (a template parameter of the burn kernel, KernelInfo.jac on the host):
+// fixed-coefficient BDF with the Jacobian every step or reused, RKC, the same two for the
+// variable-coefficient BDF, and the two every-step BDF forms with the blocked matrix-core LU.
+enum { METHOD_BDF = 0, METHOD_BDF_REUSE = 1, METHOD_RKC = 2, METHOD_BDF_VC = 3,
+       METHOD_BDF_VC_REUSE = 4, METHOD_BDF_BLU = 5, METHOD_BDF_VC_BLU = 6 };
+__host__ __device__ constexpr bool method_vc(int m)
+{
+    return m == METHOD_BDF_VC || m == METHOD_BDF_VC_REUSE || m == METHOD_BDF_VC_BLU;
+}
+__host__ __device__ constexpr int method_jac(int m)
+{
+    return (m == METHOD_BDF_REUSE || m == METHOD_BDF_VC_REUSE) ? 1 : 0;
+}
+__host__ __device__ constexpr bool method_blocked_lu(int m)
+{
+    return m == METHOD_BDF_BLU || m == METHOD_BDF_VC_BLU;
+}
+
 // Per-group LDS layout (in doubles).  Everything a zone group exchanges lives here.
 struct LdsLayout {
     int cnt, zs, ybuf, wbuf, prow, ks, rx, jbuf, vc, total;
@@ -67,8 +85,13 @@ struct LdsLayout {
 constexpr int VC_HIST = 0, VC_COUNT = QMAX, VC_L = QMAX + 1, VC_EDIV = 2 * QMAX + 2,
               VC_SLOTS = 2 * QMAX + 4;
 
+// The Jacobian rows are kept in FP32 in the mixed 48-row kernels: they only feed the
+// iteration matrix, which those kernels round to FP32 anyway, and the halved buffer lets
+// eight zones share a CU (five with FP64 rows) at 150 reactions.
+__host__ __device__ constexpr bool jac_f32(int nvp, bool mixed) { return mixed && nvp >= 48; }
+
 // nvl = lanes per zone x rows per lane (>= nvp): one slot per lane and local row.
-__host__ __device__ inline LdsLayout lds_layout(int nvp, int nvl, int nr, bool vc)
+__host__ __device__ inline LdsLayout lds_layout(int nvp, int nvl, int nr, bool vc, bool jf32)
 {
     LdsLayout o;
     int p = 0;
@@ -80,7 +103,8 @@ __host__ __device__ inline LdsLayout lds_layout(int nvp, int nvl, int nr, bool v
     o.ks = p;   p += nr;
     p = (p + 1) & ~1;
     o.rx = p;   p += 4 * nr;          // w, dw/dYa, dw/dYb, dw/dT: four columns of nr
-    o.jbuf = p; p += nvp * (nvp + 1); // Jacobian rows with an odd stride (no bank conflicts)
+    o.jbuf = p;                       // Jacobian rows with an odd stride (no bank conflicts)
+    p += jf32 ? (nvp * (nvp + 1) + 1) / 2 : nvp * (nvp + 1);
     o.vc = p;   p += vc ? VC_SLOTS : 0;
     o.total = (p + 1) & ~1;
     return o;
@@ -91,7 +115,7 @@ struct KernelInfo {
     int nvp;          // padded number of variables the kernel handles (nv <= nvp)
     int lanes;        // lanes per zone
     int mixed;        // 0: FP64 LU, 1: FP32 LU
-    int jac;          // method: 0 BDF with J every step, 1 BDF with reuse, 2 RKC
+    int jac;          // method (METHOD_*)
     const void *fn;   // __global__ function
 };
 

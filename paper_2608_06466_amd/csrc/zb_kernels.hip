@@ -10,6 +10,7 @@ namespace zb {
 int kernels_04(const KernelInfo **out);
 int kernels_16(const KernelInfo **out);
 int kernels_14(const KernelInfo **out);
+int kernels_48b(const KernelInfo **out);
 int kernels_14r(const KernelInfo **out);
 int kernels_14v(const KernelInfo **out);
 int kernels_14vr(const KernelInfo **out);
@@ -62,6 +63,7 @@ int kernel_table(const KernelInfo **out)
         add(kernels_04);
         add(kernels_16);
         add(kernels_14);
+        add(kernels_48b);
         add(kernels_14r);
         add(kernels_14v);
         add(kernels_14vr);

@@ -397,6 +397,10 @@ extern "C" zb_err zb_server_create(zb_context *ctx, const zb_server_opts *so, zb
         return fail(ZB_EINVAL, "retry_jac %d", bo.retry_jac);
     if (bo.retry && bo.integrator == ZB_RKC && bo.retry_jac == ZB_RETRY_JAC_FD)
         return fail(ZB_EINVAL, "the finite-difference retry Jacobian is a BDF option");
+    {
+        const zb_err e = check_lu(&bo, bo.precision);
+        if (e != ZB_OK) return e;
+    }
     DeviceGuard g(ctx->device);
     zb_server *S = new (std::nothrow) zb_server();
     if (!S) return fail(ZB_ENOMEM, "host allocation failed");
@@ -449,8 +453,8 @@ extern "C" zb_err zb_server_submit(zb_server *S, const zb_network *net, const do
         return fail(ZB_EINVAL, "dt, rtol and atol must be finite and > 0");
     const int row = net->dn.ns + 1;
     const int lanes = lanes_for(S->ctx, net, S->opts.precision, &S->opts);
-    const KernelInfo *k = find_kernel(net->dn.nv, lanes, S->opts.precision == ZB_MIXED,
-                                      method_of(&S->opts));
+    const KernelInfo *k = kernel_for(net->dn.nv, lanes, S->opts.precision == ZB_MIXED,
+                                     method_of(&S->opts));
     if (!k) return fail(ZB_EUNSUPPORTED, "no kernel for nv=%d with %d lanes", net->dn.nv, lanes);
     auto al = [](size_t b) { return (b + ALIGN - 1) & ~(ALIGN - 1); };
     size_t bytes = al(sizeof(double) * row * (size_t)zones) + al(sizeof(int32_t) * (size_t)zones) +

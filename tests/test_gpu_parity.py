@@ -642,3 +642,74 @@ def test_variable_coefficient_bdf_robertson(zbm, lanes):
         out.append((t.cpu().numpy(), status.cpu().numpy(), stats.cpu().numpy()))
     check(f"robertson variable-coefficient L{lanes}", out[0], (ref, fine), 1e-8, 1e-12, 3, out[1])
     net.close()
+
+
+def _blu_case(which):
+    """(network, zones, lanes) of a blocked-LU case: the 48-variable network of the batched
+    workload, networks of 40 and 33 variables (identity rows past nv; a last panel of one
+    step), and the 14-variable network forced onto the 48-row kernel (a first panel of 14
+    steps, two empty panels)."""
+    if which == "nv48":
+        ns, R, seed = W.CONFIG3_NETS[2]
+        return W.random_network(ns, R, seed), 48, 0, W.CONFIG3_T_RANGE, "loguniform"
+    if which == "nv40":
+        return W.random_network(39, 120, 612), 48, 0, W.CONFIG3_T_RANGE, "loguniform"
+    if which == "nv33":
+        return W.random_network(32, 100, 613), 48, 0, W.CONFIG3_T_RANGE, "loguniform"
+    return W.config2_network(), 64, 64, (1e3, 5e3), "uniform"
+
+
+@pytest.mark.parametrize("which,integrator", [("nv48", "bdf"), ("nv48", "bdf_variable"),
+                                               ("nv40", "bdf"), ("nv33", "bdf"),
+                                               ("nv14_on_64_lanes", "bdf")])
+def test_blocked_mfma_lu_parity(zbm, which, integrator):
+    """The blocked LU with its trailing updates on FP32 MFMA (lu='mfma', mixed precision)
+    against the FP64 oracle of the same integrator form: same statuses, results within the
+    widened bar (each side's own error from its run at rtol/100)."""
+    zb, ctx = zbm
+    net_d, n, lanes, Tr, Td = _blu_case(which)
+    st = W.random_zones(net_d, n, seed=783, T_range=Tr, T_dist=Td)
+    nv = net_d["n_species"] + net_d["thermal"]
+    form = "variable" if integrator == "bdf_variable" else "fixed"
+    ref = oracle.burn(net_d, st, 1.0, 1e-8, 1e-12, form=form)
+    fine = oracle.burn(net_d, st, 1.0, 1e-10, 1e-14, form=form, max_steps=10000000)
+    net = zb.Network(ctx, net_d)
+    out = []
+    for rt, at, ms in ((1e-8, 1e-12, 0), (1e-10, 1e-14, 10000000)):
+        t = torch.tensor(st, device="cuda:0")
+        status, stats = zb.burn(ctx, net, t, 1.0, rt, at, precision="mixed", lanes=lanes,
+                                max_steps=ms, integrator=integrator, lu="mfma")
+        assert zb.sync(ctx) == 0
+        out.append((t.cpu().numpy(), status.cpu().numpy(), stats.cpu().numpy()))
+    check(f"{which} blocked MFMA LU {integrator}", out[0], (ref, fine), 1e-8, 1e-12, nv, out[1])
+    net.close()
+
+
+def test_blocked_mfma_lu_options_are_checked(zbm):
+    """lu='mfma' needs the mixed precision, the every-step Jacobian and a BDF integrator
+    (EINVAL otherwise).  A network on fewer than 64 lanes per zone has no blocked form and
+    takes the vector-unit LU: the same results bit for bit."""
+    zb, ctx = zbm
+    ns, R, seed = W.CONFIG3_NETS[2]
+    net_d = W.random_network(ns, R, seed)
+    net = zb.Network(ctx, net_d)
+    t = torch.tensor(W.random_zones(net_d, 4, seed=5), device="cuda:0")
+    for kw in (dict(precision="fp64"), dict(precision="mixed", jac_policy=1),
+               dict(precision="fp64", integrator="rkc"), dict(precision="mixed", integrator="rkc")):
+        with pytest.raises(zb.ZoneburnError) as e:
+            zb.burn(ctx, net, t, 1.0, 1e-6, 1e-10, lu="mfma", **kw)
+        assert e.value.code == zb.EINVAL, kw
+    with pytest.raises(ValueError):
+        zb.burn(ctx, net, t, 1.0, 1e-6, 1e-10, precision="mixed", lu="blocked")
+    small = zb.Network(ctx, W.config2_network())
+    st = W.config2(64)["state"]
+    res = []
+    for lu in ("mfma", "valu"):
+        ts = torch.tensor(st, device="cuda:0")
+        status, stats = zb.burn(ctx, small, ts, 1.0, 1e-8, 1e-12, precision="mixed", lu=lu)
+        assert zb.sync(ctx) == 0
+        res.append((ts.cpu().numpy(), status.cpu().numpy(), stats.cpu().numpy()))
+    for a, b in zip(*res):
+        assert np.array_equal(a, b)
+    small.close()
+    net.close()
