@@ -442,10 +442,23 @@ struct Ctx {
     int64_t zone;
     int jac_policy;
     bool lu_blocked;         // the blocked matrix-core LU (48-row FP32 kernels)
+    bool rates;              // per-reaction rate factors in LDS (else all 1)
 };
 
 template <int NVP, int L>
 __device__ __forceinline__ int row_of(const Ctx &c, int s) { return c.gl + L * s; }
+
+// Per-reaction rate factors in LDS: always, except in the trimmed layout of a launch without
+// rate scales (all factors 1).
+template <int NVP, int L, class LT>
+__device__ __forceinline__ bool rates_in_lds(const Ctx &c)
+{
+    constexpr int RPL = (NVP + L - 1) / L;
+    if constexpr (lds_trim(L, RPL, jac_f32(NVP, sizeof(LT) == 4)))
+        return c.rates;
+    else
+        return true;
+}
 
 // Element type of the Jacobian rows in LDS.
 template <int NVP, class LT>
@@ -527,7 +540,7 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
         const double ya = ybuf[ix.x];
         const double yb0 = ix.y >= 0 ? ybuf[ix.y] : 1.0;
         const double yb = (ya < 0.0 && yb0 < 0.0) ? -yb0 : yb0;
-        double k = ks[r];
+        double k = rates_in_lds<NVP, L, LT>(c) ? ks[r] : 1.0;
         if (N.thermal) k *= exp(pr.x + pr.y * lnT - pr.z * iT);
         double kYb = k * yb;
         double w = kYb * ya;
@@ -1123,8 +1136,18 @@ __device__ __forceinline__ void set_weights(const Ctx &c, Zone<NVP, L, LT> &z)
     }
 }
 
-// The history copy lives in LDS, one slot per (lane, order, local row); only
-// this lane reads it back, so no exchange ordering is involved.
+// The history copy lives in LDS, one slot per (order, lane, local row), or per (order, row)
+// in the trimmed layout; only this lane reads it back, so no exchange ordering is involved.
+// Lanes past the last row hold no row (their history is identically zero) and no slot.
+template <int NVP, int L, int RPL, class LT>
+__device__ __forceinline__ int zs_slot(int gl, int j, int s)
+{
+    if constexpr (lds_trim(L, RPL, jac_f32(NVP, sizeof(LT) == 4)))
+        return gl < NVP ? j * NVP + gl : -1;
+    else
+        return (j * RPL + s) * L + gl;
+}
+
 template <int NVP, int L, class LT>
 __device__ __forceinline__ void save_history(const Ctx &c, const Zone<NVP, L, LT> &z)
 {
@@ -1134,7 +1157,10 @@ __device__ __forceinline__ void save_history(const Ctx &c, const Zone<NVP, L, LT
     for (int j = 0; j <= QMAX; ++j)
         if (j <= z.q)
 #pragma unroll
-            for (int s = 0; s < RPL; ++s) zs[(j * RPL + s) * L + c.gl] = z.Z[j][s];
+            for (int s = 0; s < RPL; ++s) {
+                const int q = zs_slot<NVP, L, RPL, LT>(c.gl, j, s);
+                if (q >= 0) zs[q] = z.Z[j][s];
+            }
 }
 
 template <int NVP, int L, class LT>
@@ -1146,7 +1172,10 @@ __device__ __forceinline__ void restore_history(const Ctx &c, Zone<NVP, L, LT> &
     for (int j = 0; j <= QMAX; ++j)
         if (j <= z.q)
 #pragma unroll
-            for (int s = 0; s < RPL; ++s) z.Z[j][s] = zs[(j * RPL + s) * L + c.gl];
+            for (int s = 0; s < RPL; ++s) {
+                const int q = zs_slot<NVP, L, RPL, LT>(c.gl, j, s);
+                if (q >= 0) z.Z[j][s] = zs[q];
+            }
 }
 
 enum { RUNNING = -1 };
@@ -1159,9 +1188,11 @@ __device__ __forceinline__ int zone_start(const Ctx &c, Zone<NVP, L, LT> &z)
     const DevNet &N = c.net;
     const double *row = c.state + c.zone * (N.ns + 1);
     double *ks = c.S + c.lay.ks;
-    for (int r = c.gl; r < N.nr; r += L) {
-        double s = c.scale ? c.scale[c.zone * N.nr + r] : 1.0;
-        ks[r] = N.thermal ? s : s * exp(N.par[r].x);
+    if (rates_in_lds<NVP, L, LT>(c)) {
+        for (int r = c.gl; r < N.nr; r += L) {
+            double s = c.scale ? c.scale[c.zone * N.nr + r] : 1.0;
+            ks[r] = N.thermal ? s : s * exp(N.par[r].x);
+        }
     }
     bool bad = false;
 #pragma unroll
@@ -1400,7 +1431,7 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
         for (int s = 0; s < RPL; ++s) {
             const int i = row_of<NVP, L>(c, s);
             if (i < c.net.ns && z.y[s] < -z.atol) {
-                const double old = zs[s * L + c.gl];   // Z_0 before the prediction
+                const double old = zs[zs_slot<NVP, L, RPL, LT>(c.gl, 0, s)];   // Z_0 before the prediction
                 feas = fmin(feas, (old + z.atol) / (old - z.y[s]));
             }
         }
@@ -1730,8 +1761,8 @@ __device__ __forceinline__ T uniform(T v)
 }
 
 // Segment data for the wave (the wave works on one segment at a time, so it is uniform).
-__device__ __forceinline__ void load_segment(Ctx &c, const BurnArgs &A, int seg, int nvp, int nvl,
-                                             bool vc, bool jf32)
+__device__ __forceinline__ void load_segment(Ctx &c, const BurnArgs &A, int seg, int nvp, int L,
+                                             int rpl, bool vc, bool jf32)
 {
     // seg is wave-uniform: scalar loads from the kernel-argument segment
     const BurnArgs *pa = (const BurnArgs *)__builtin_amdgcn_kernarg_segment_ptr();
@@ -1754,7 +1785,8 @@ __device__ __forceinline__ void load_segment(Ctx &c, const BurnArgs &A, int seg,
     c.rtol = uniform(S.rtol);
     c.atol = uniform(S.atol);
     c.dt = uniform(S.dt);
-    c.lay = lds_layout(nvp, nvl, A.max_nr, vc, jf32);
+    c.rates = pa->rates_lds != 0;
+    c.lay = lds_layout(nvp, L, rpl, A.max_nr, vc, jf32, c.rates);
 }
 
 // Persistent kernel.  Each wave works through the segments in order; within a
@@ -1791,7 +1823,7 @@ void burn_kernel(BurnArgs A)
     c.lu_blocked = method_blocked_lu(JP);   // a constant: each
                          // method is its own kernel (the reuse keeps the
                          // factors live across steps, which costs registers)
-    load_segment(c, A, seg, NVP, L * RPL, method_vc(JP), jac_f32(NVP, sizeof(LT) == 4));
+    load_segment(c, A, seg, NVP, L, RPL, method_vc(JP), jac_f32(NVP, sizeof(LT) == 4));
     c.S = smem + g * c.lay.total;
     int64_t zones = uniform(A.seg[0].zones);
     bool need = true, dry = false;
@@ -1818,7 +1850,7 @@ void burn_kernel(BurnArgs A)
         }
         if (__ballot(!dry) == 0) {
             if (++seg >= A.nseg) break;
-            load_segment(c, A, seg, NVP, L * RPL, method_vc(JP), jac_f32(NVP, sizeof(LT) == 4));
+            load_segment(c, A, seg, NVP, L, RPL, method_vc(JP), jac_f32(NVP, sizeof(LT) == 4));
             c.S = smem + g * c.lay.total;
             {
                 const BurnArgs *pa = (const BurnArgs *)__builtin_amdgcn_kernarg_segment_ptr();

@@ -190,12 +190,14 @@ extern "C" zb_err zb_network_info(const zb_network *n, int32_t *n_var, int32_t *
 
 // ------------------------------------------------------------- kernel choice
 
-static size_t launch_lds(const KernelInfo *k, int max_nr)
+// LDS of a launch; rates as in lds_layout (true is the larger, for choices made before the
+// segments are known).
+static size_t launch_lds(const KernelInfo *k, int max_nr, bool rates = true)
 {
     const int G = 64 / k->lanes;
     const int rpl = (k->nvp + k->lanes - 1) / k->lanes;
-    const LdsLayout lay = lds_layout(k->nvp, k->lanes * rpl, max_nr, method_vc(k->jac),
-                                     jac_f32(k->nvp, k->mixed != 0));
+    const LdsLayout lay = lds_layout(k->nvp, k->lanes, rpl, max_nr, method_vc(k->jac),
+                                     jac_f32(k->nvp, k->mixed != 0), rates);
     return (size_t)G * lay.total * sizeof(double);
 }
 
@@ -345,6 +347,7 @@ static zb_err launch_segments(zb_context *ctx, const KernelInfo *k, const zb_seg
     memset(&A, 0, sizeof A);
     int64_t total = 0;
     int max_nr = 0;
+    bool rates = false;
     for (int i = 0; i < n; ++i) {
         Segment &S = A.seg[i];
         S.net = segs[i].net->dn;
@@ -359,6 +362,7 @@ static zb_err launch_segments(zb_context *ctx, const KernelInfo *k, const zb_seg
         S.atol = segs[i].atol;
         total += segs[i].zones;
         max_nr = std::max(max_nr, S.net.nr);
+        rates = rates || S.scale != nullptr || !S.net.thermal;
     }
     if (total == 0) return ZB_OK;
     A.nseg = n;
@@ -369,11 +373,12 @@ static zb_err launch_segments(zb_context *ctx, const KernelInfo *k, const zb_seg
     A.retry_rtol = ro.retry_rtol;
     A.retry_atol = ro.retry_atol;
     A.retry_jac = ro.retry_jac;
+    A.rates_lds = rates ? 1 : 0;
     A.queue = queue;
     A.nfail = nfail;
 
     const int G = 64 / k->lanes;
-    const size_t lds = launch_lds(k, max_nr);
+    const size_t lds = launch_lds(k, max_nr, rates);
     if (lds > 160 * 1024) return fail(ZB_EUNSUPPORTED, "LDS need %zu bytes exceeds 160 KiB", lds);
     int per_cu = 0;
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k->fn, 64, lds));

@@ -51,6 +51,8 @@ struct BurnArgs {
     int max_steps;
     int retry, retry_max_steps;    // zone-by-zone retry of failed zones (0: off)
     int retry_jac;                 // retry Jacobian: 0 analytic, 1 finite differences
+    int rates_lds;                 // 1: per-reaction rate factors kept in LDS (some segment
+                                   // has rate scales or a network without temperature)
     double retry_rtol, retry_atol;
     unsigned long long *queue;     // [nseg] next zone of each segment (zeroed before the launch)
     unsigned long long *nfail;     // zones that ended with a non-OK status
@@ -90,17 +92,31 @@ constexpr int VC_HIST = 0, VC_COUNT = QMAX, VC_L = QMAX + 1, VC_EDIV = 2 * QMAX 
 // eight zones share a CU (five with FP64 rows) at 150 reactions.
 __host__ __device__ constexpr bool jac_f32(int nvp, bool mixed) { return mixed && nvp >= 48; }
 
-// nvl = lanes per zone x rows per lane (>= nvp): one slot per lane and local row.
-__host__ __device__ inline LdsLayout lds_layout(int nvp, int nvl, int nr, bool vc, bool jf32)
+// The trimmed layout of the FP64 whole-wave kernels (one row a lane), the one class whose
+// LDS, not its registers, bounds the zones a CU holds (five of a possible eight at 48 rows
+// and 150 reactions; six trimmed): the history copy has one slot per row instead of per
+// lane, there is no pivot-row buffer (pivot rows are read from registers), and the
+// per-reaction rate factors take no space when they are all 1.
+__host__ __device__ constexpr bool lds_trim(int L, int rpl, bool jf32)
 {
+    return L == 64 && rpl == 1 && !jf32;
+}
+
+// L lanes per zone with rpl rows each.  rates: the per-reaction rate factors (the zone's rate
+// scales, or a network's constant rates when it has no temperature) are needed; without
+// rate scales and with a temperature variable they are all 1.
+__host__ __device__ inline LdsLayout lds_layout(int nvp, int L, int rpl, int nr, bool vc,
+                                                bool jf32, bool rates)
+{
+    const bool trim = lds_trim(L, rpl, jf32);
     LdsLayout o;
     int p = 0;
     o.cnt = p;  p += 4;               // counters of a zone's first run while it is retried
-    o.zs = p;   p += (QMAX + 1) * nvl;
+    o.zs = p;   p += (QMAX + 1) * (trim ? nvp : L * rpl);
     o.ybuf = p; p += nvp;
     o.wbuf = p; p += nvp;
-    o.prow = p; p += nvp;
-    o.ks = p;   p += nr;
+    o.prow = p; p += trim ? 0 : nvp;
+    o.ks = p;   p += (trim && !rates) ? 0 : nr;
     p = (p + 1) & ~1;
     o.rx = p;   p += 4 * nr;          // w, dw/dYa, dw/dYb, dw/dT: four columns of nr
     o.jbuf = p;                       // Jacobian rows with an odd stride (no bank conflicts)
