@@ -1140,10 +1140,19 @@ __device__ __forceinline__ void set_weights(const Ctx &c, Zone<NVP, L, LT> &z)
 // in the trimmed layout; only this lane reads it back, so no exchange ordering is involved.
 // Lanes past the last row hold no row (their history is identically zero) and no slot.
 template <int NVP, int L, int RPL, class LT>
+__device__ __forceinline__ bool zs_has(int gl)
+{
+    if constexpr (lds_trim(L, RPL, jac_f32(NVP, sizeof(LT) == 4)))
+        return gl < NVP;
+    else
+        return true;
+}
+
+template <int NVP, int L, int RPL, class LT>
 __device__ __forceinline__ int zs_slot(int gl, int j, int s)
 {
     if constexpr (lds_trim(L, RPL, jac_f32(NVP, sizeof(LT) == 4)))
-        return gl < NVP ? j * NVP + gl : -1;
+        return j * NVP + gl;
     else
         return (j * RPL + s) * L + gl;
 }
@@ -1158,8 +1167,7 @@ __device__ __forceinline__ void save_history(const Ctx &c, const Zone<NVP, L, LT
         if (j <= z.q)
 #pragma unroll
             for (int s = 0; s < RPL; ++s) {
-                const int q = zs_slot<NVP, L, RPL, LT>(c.gl, j, s);
-                if (q >= 0) zs[q] = z.Z[j][s];
+                if (zs_has<NVP, L, RPL, LT>(c.gl)) zs[zs_slot<NVP, L, RPL, LT>(c.gl, j, s)] = z.Z[j][s];
             }
 }
 
@@ -1173,8 +1181,7 @@ __device__ __forceinline__ void restore_history(const Ctx &c, Zone<NVP, L, LT> &
         if (j <= z.q)
 #pragma unroll
             for (int s = 0; s < RPL; ++s) {
-                const int q = zs_slot<NVP, L, RPL, LT>(c.gl, j, s);
-                if (q >= 0) z.Z[j][s] = zs[q];
+                if (zs_has<NVP, L, RPL, LT>(c.gl)) z.Z[j][s] = zs[zs_slot<NVP, L, RPL, LT>(c.gl, j, s)];
             }
 }
 

@@ -51,11 +51,11 @@ struct BurnArgs {
     int max_steps;
     int retry, retry_max_steps;    // zone-by-zone retry of failed zones (0: off)
     int retry_jac;                 // retry Jacobian: 0 analytic, 1 finite differences
-    int rates_lds;                 // 1: per-reaction rate factors kept in LDS (some segment
-                                   // has rate scales or a network without temperature)
     double retry_rtol, retry_atol;
     unsigned long long *queue;     // [nseg] next zone of each segment (zeroed before the launch)
     unsigned long long *nfail;     // zones that ended with a non-OK status
+    int rates_lds;                 // 1: per-reaction rate factors kept in LDS (some segment
+                                   // has rate scales or a network without temperature)
 };
 
 // Kernel methods (a template parameter of the burn kernel, KernelInfo.jac on the host):

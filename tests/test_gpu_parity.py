@@ -713,3 +713,43 @@ def test_blocked_mfma_lu_options_are_checked(zbm):
         assert np.array_equal(a, b)
     small.close()
     net.close()
+
+
+def test_fp64_whole_wave_rate_factors(zbm):
+    """The FP64 48-row kernel keeps per-reaction rate factors in LDS only when its launch
+    needs them (trimmed layout): a thermal network with rate scales, a network without
+    temperature (constant rates), each against the oracle; and one launch of a scaled and an
+    unscaled segment, bitwise equal to the two separate burns (without scales the factors
+    are 1 either way)."""
+    zb, ctx = zbm
+    ns, R, seed = W.CONFIG3_NETS[2]
+    net_t = W.random_network(ns, R, seed)
+    net_c = W.random_network(48, 150, 614, thermal=False, log10A=(0.0, 4.0))
+    rng = np.random.default_rng(615)
+    st_t = W.random_zones(net_t, 32, seed=616, T_range=W.CONFIG3_T_RANGE, T_dist="loguniform")
+    sc_t = np.exp(rng.normal(0.0, 0.5, (32, R)))
+    st_c = W.random_zones(net_c, 32, seed=617)
+    single = {}
+    for name, net_d, st, sc in (("scaled", net_t, st_t, sc_t), ("unscaled", net_t, st_t, None),
+                                ("constant-rate", net_c, st_c, None)):
+        nv = net_d["n_species"] + net_d["thermal"]
+        ref = oracle_ref(net_d, st, 1.0, 1e-8, 1e-12, scale=sc)
+        g = run_gpu(zb, ctx, net_d, st, 1.0, 1e-8, 1e-12, scale=sc)
+        gf = run_gpu(zb, ctx, net_d, st, 1.0, 1e-10, 1e-14, scale=sc, max_steps=10000000)
+        check(f"48-row FP64 {name}", g, ref, 1e-8, 1e-12, nv, gf)
+        single[name] = g
+    net = zb.Network(ctx, net_t)
+    ts = [torch.tensor(st_t, device="cuda:0") for _ in range(2)]
+    status = [torch.empty(32, dtype=torch.int32, device="cuda:0") for _ in range(2)]
+    stats = [torch.empty((32, 7), dtype=torch.int32, device="cuda:0") for _ in range(2)]
+    sc = torch.tensor(sc_t, device="cuda:0")
+    zb.burn_batch(ctx, [dict(net=net, state=ts[0], dt=1.0, rtol=1e-8, atol=1e-12, rate_scale=sc,
+                             status=status[0], stats=stats[0]),
+                        dict(net=net, state=ts[1], dt=1.0, rtol=1e-8, atol=1e-12,
+                             status=status[1], stats=stats[1])])
+    assert zb.sync(ctx) == 0
+    for k, name in enumerate(("scaled", "unscaled")):
+        assert np.array_equal(ts[k].cpu().numpy(), single[name][0]), name
+        assert np.array_equal(status[k].cpu().numpy(), single[name][1]), name
+        assert np.array_equal(stats[k].cpu().numpy(), single[name][2]), name
+    net.close()
