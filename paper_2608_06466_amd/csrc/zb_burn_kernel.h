@@ -932,9 +932,17 @@ __device__ __forceinline__ void lu_factor(const Ctx &c, Zone<NVP, L, LT> &z)
     const int nv = own_copy(c.net.nv);
     sfor<0, RPL>([&](auto S) { z.pstep[S] = 127; });
     z.pivlane = c.gl;
-    sfor<0, NVP>([&](auto K) {
+    // Whole-wave zones test nv once per 8 steps, not per step, so 8 steps form one block the
+    // scheduler can overlap; the steps run past nv up to the next multiple of 8 are harmless:
+    // rows past nv are identity rows (pivot 1, multipliers 0 elsewhere, nothing changes).
+    // Lanes past nvp hold zero rows and never pivot.
+    constexpr bool WW = L == 64 && RPL == 1;
+    const int nsearch = WW ? NVP : nv;
+    auto step = [&](auto K) {
         constexpr int k = K;
-        if (k >= nv) return;
+        if constexpr (!WW) {
+            if (k >= nv) return;
+        }
         // the search runs in the factor's precision (FP32 values compare the same
         // way as their FP64 widenings, so the pivot is the same)
         LT bv = LT(-1);
@@ -942,7 +950,7 @@ __device__ __forceinline__ void lu_factor(const Ctx &c, Zone<NVP, L, LT> &z)
         sfor<0, RPL>([&](auto S) {
             int i = row_of<NVP, L>(c, S);
             LT a = fabs(z.M[S][k]);
-            if (z.pstep[S] > k && i < nv && a > bv) {
+            if (z.pstep[S] > k && i < nsearch && a > bv) {
                 bv = a;
                 bi = i;
             }
@@ -1019,7 +1027,15 @@ __device__ __forceinline__ void lu_factor(const Ctx &c, Zone<NVP, L, LT> &z)
             if (c.gl == k) z.pivlane = p;
         }
         lds_fence();
-    });
+    };
+    if constexpr (WW) {
+        static_assert(NVP % 8 == 0, "whole-wave LU steps in chunks of 8");
+        sfor<0, NVP / 8>([&](auto C) {
+            if (8 * C < nv) sfor<8 * C, 8 * C + 8>(step);
+        });
+    } else {
+        sfor<0, NVP>(step);
+    }
     if constexpr (RPL == 1) {
         // Move pivot row k to group lane k: the factors become those of P M in natural
         // order, and the triangular solves broadcast from a fixed lane.
