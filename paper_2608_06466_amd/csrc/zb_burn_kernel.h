@@ -747,6 +747,26 @@ __device__ __forceinline__ void form_M(const Ctx &c, Zone<NVP, L, LT> &z, double
 
 // --------------------------------------------------------------- LU / solve
 
+// Runs f(k) for the elimination steps k of nv variables, testing nv once per 8 steps instead
+// of per step, so that 8 steps form one block the scheduler can overlap.  Steps past nv up to
+// the next multiple of 8 (and nvp) run too; they are harmless in the LU and the solves: the
+// rows of M past nv are identity rows (pivot 1, every other multiplier 0) and the right-hand
+// side is zero there.  REV runs the steps backwards (nvp-1 first).
+template <int NVP, bool REV = false, class F>
+__device__ __forceinline__ void steps8(int nv, F &&f)
+{
+    sfor<0, (NVP + 7) / 8>([&](auto C) {
+        constexpr int a = 8 * C, b = (8 * C + 8 < NVP) ? 8 * C + 8 : NVP;
+        if constexpr (!REV) {
+            if (a < nv) sfor<a, b>(f);
+        } else {
+            // chunk C holds k = NVP-1-kk for kk in [a, b)
+            if (NVP - b < nv)
+                sfor<a, b>([&](auto KK) { f(std::integral_constant<int, NVP - 1 - KK>{}); });
+        }
+    });
+}
+
 typedef float zb_v16f __attribute__((ext_vector_type(16)));
 typedef float zb_v4f __attribute__((ext_vector_type(4)));
 
@@ -932,17 +952,9 @@ __device__ __forceinline__ void lu_factor(const Ctx &c, Zone<NVP, L, LT> &z)
     const int nv = own_copy(c.net.nv);
     sfor<0, RPL>([&](auto S) { z.pstep[S] = 127; });
     z.pivlane = c.gl;
-    // Whole-wave zones test nv once per 8 steps, not per step, so 8 steps form one block the
-    // scheduler can overlap; the steps run past nv up to the next multiple of 8 are harmless:
-    // rows past nv are identity rows (pivot 1, multipliers 0 elsewhere, nothing changes).
-    // Lanes past nvp hold zero rows and never pivot.
-    constexpr bool WW = L == 64 && RPL == 1;
-    const int nsearch = WW ? NVP : nv;
+    // The steps run in chunks of 8 (steps8); lanes past nvp hold zero rows and never pivot.
     auto step = [&](auto K) {
         constexpr int k = K;
-        if constexpr (!WW) {
-            if (k >= nv) return;
-        }
         // the search runs in the factor's precision (FP32 values compare the same
         // way as their FP64 widenings, so the pivot is the same)
         LT bv = LT(-1);
@@ -950,7 +962,7 @@ __device__ __forceinline__ void lu_factor(const Ctx &c, Zone<NVP, L, LT> &z)
         sfor<0, RPL>([&](auto S) {
             int i = row_of<NVP, L>(c, S);
             LT a = fabs(z.M[S][k]);
-            if (z.pstep[S] > k && i < nsearch && a > bv) {
+            if (z.pstep[S] > k && i < NVP && a > bv) {
                 bv = a;
                 bi = i;
             }
@@ -1028,14 +1040,7 @@ __device__ __forceinline__ void lu_factor(const Ctx &c, Zone<NVP, L, LT> &z)
         }
         lds_fence();
     };
-    if constexpr (WW) {
-        static_assert(NVP % 8 == 0, "whole-wave LU steps in chunks of 8");
-        sfor<0, NVP / 8>([&](auto C) {
-            if (8 * C < nv) sfor<8 * C, 8 * C + 8>(step);
-        });
-    } else {
-        sfor<0, NVP>(step);
-    }
+    steps8<NVP>(nv, step);
     if constexpr (RPL == 1) {
         // Move pivot row k to group lane k: the factors become those of P M in natural
         // order, and the triangular solves broadcast from a fixed lane.
@@ -1058,15 +1063,13 @@ __device__ __forceinline__ void lu_solve(const Ctx &c, const Zone<NVP, L, LT> &z
         const int src = (int)(threadIdx.x & (64 - L)) + z.pivlane;
         const double bp = gather(b[0], src);
         LT v = MIXED ? (LT)(bp * (double)z.rs[0]) : (LT)bp;
-        sfor<0, NVP>([&](auto K) {
+        steps8<NVP>(nv, [&](auto K) {
             constexpr int k = K;
-            if (k >= nv) return;
             const LT yk = bcast_k<L, k>(v);
             if (after(c.gl, v) > k) v = fma(-z.M[0][k], yk, v);
         });
-        sfor<0, NVP>([&](auto KK) {
-            constexpr int k = NVP - 1 - KK;
-            if (k >= nv) return;
+        steps8<NVP, true>(nv, [&](auto K) {
+            constexpr int k = K;
             const LT xk = bcast_k<L, k>(v * z.dinv[0]);
             if (after(c.gl, v) < k) v = fma(-z.M[0][k], xk, v);
         });
@@ -1080,9 +1083,8 @@ __device__ __forceinline__ void lu_solve(const Ctx &c, const Zone<NVP, L, LT> &z
         bb[S] = MIXED ? (LT)(b[S] * (double)z.rs[S]) : (LT)b[S];
         x[S] = LT(0);
     });
-    sfor<0, NVP>([&](auto K) {
+    steps8<NVP>(nv, [&](auto K) {
         constexpr int k = K;
-        if (k >= nv) return;
         LT v = LT(0);
         bool own = false;
         int ps[RPL];
@@ -1096,9 +1098,8 @@ __device__ __forceinline__ void lu_solve(const Ctx &c, const Zone<NVP, L, LT> &z
             if (ps[S] > k) bb[S] = fma(-z.M[S][k], zk, bb[S]);
         });
     });
-    sfor<0, NVP>([&](auto KK) {
-        constexpr int k = NVP - 1 - KK;
-        if (k >= nv) return;
+    steps8<NVP, true>(nv, [&](auto K) {
+        constexpr int k = K;
         LT v = LT(0);
         bool own = false;
         int ps[RPL];
