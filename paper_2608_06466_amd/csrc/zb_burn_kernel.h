@@ -1127,13 +1127,13 @@ template <int NVP, int L, class LT>
 __device__ __forceinline__ void rescale(Zone<NVP, L, LT> &z, double eta)
 {
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
+    // every order: the columns past q are zero (zeroed at the start, on an order decrease
+    // and on a restart at order 1)
     double r = eta;
 #pragma unroll
     for (int j = 1; j <= QMAX; ++j) {
-        if (j <= z.q) {
 #pragma unroll
-            for (int s = 0; s < RPL; ++s) z.Z[j][s] *= r;
-        }
+        for (int s = 0; s < RPL; ++s) z.Z[j][s] *= r;
         r *= eta;
     }
 }
@@ -1181,11 +1181,10 @@ __device__ __forceinline__ void save_history(const Ctx &c, const Zone<NVP, L, LT
     double *zs = c.S + c.lay.zs;
 #pragma unroll
     for (int j = 0; j <= QMAX; ++j)
-        if (j <= z.q)
 #pragma unroll
-            for (int s = 0; s < RPL; ++s) {
-                if (zs_has<NVP, L, RPL, LT>(c.gl)) zs[zs_slot<NVP, L, RPL, LT>(c.gl, j, s)] = z.Z[j][s];
-            }
+        for (int s = 0; s < RPL; ++s) {
+            if (zs_has<NVP, L, RPL, LT>(c.gl)) zs[zs_slot<NVP, L, RPL, LT>(c.gl, j, s)] = z.Z[j][s];
+        }
 }
 
 template <int NVP, int L, class LT>
@@ -1195,11 +1194,10 @@ __device__ __forceinline__ void restore_history(const Ctx &c, Zone<NVP, L, LT> &
     const double *zs = c.S + c.lay.zs;
 #pragma unroll
     for (int j = 0; j <= QMAX; ++j)
-        if (j <= z.q)
 #pragma unroll
-            for (int s = 0; s < RPL; ++s) {
-                if (zs_has<NVP, L, RPL, LT>(c.gl)) z.Z[j][s] = zs[zs_slot<NVP, L, RPL, LT>(c.gl, j, s)];
-            }
+        for (int s = 0; s < RPL; ++s) {
+            if (zs_has<NVP, L, RPL, LT>(c.gl)) z.Z[j][s] = zs[zs_slot<NVP, L, RPL, LT>(c.gl, j, s)];
+        }
 }
 
 enum { RUNNING = -1 };
@@ -1379,14 +1377,14 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
     }
     set_weights(c, z);
     save_history(c, z);
-    // prediction: Pascal triangle
+    // prediction: Pascal triangle, over every order (the columns past q are zero, so the
+    // extra additions add zeros: no branch on q)
 #pragma unroll
     for (int k = 0; k < QMAX; ++k)
 #pragma unroll
         for (int j = QMAX; j > k; --j)
-            if (k < z.q && j <= z.q)
 #pragma unroll
-                for (int s = 0; s < RPL; ++s) z.Z[j - 1][s] += z.Z[j][s];
+            for (int s = 0; s < RPL; ++s) z.Z[j - 1][s] += z.Z[j][s];
 
     const double h = z.h;
     double l0, ediv;
@@ -1471,6 +1469,12 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
         z.h *= eta;
         if (z.nefc >= 3) {
             z.q = 1;
+            // the columns past the order stay zero (the prediction and the history copy run
+            // over every order)
+#pragma unroll
+            for (int j = 2; j <= QMAX; ++j)
+#pragma unroll
+                for (int s = 0; s < RPL; ++s) z.Z[j][s] = 0.0;
             if constexpr (VC) {
                 // the restarted history is a tangent, not past values
                 if (c.gl == 0) c.S[c.lay.vc + VC_COUNT] = 0.0;
@@ -1493,10 +1497,12 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
     const double H = VC ? 1.0 / l0 : harmonic(z.q);
 #pragma unroll
     for (int j = 1; j <= QMAX; ++j) {
-        if (j <= z.q) {
-            double lj = VC ? c.S[c.lay.vc + VC_L + j] : lcoef(z.q, j);
+        const double lj = VC ? c.S[c.lay.vc + VC_L + j] : lcoef(z.q, j);
+        const bool in = j <= z.q;
 #pragma unroll
-            for (int s = 0; s < RPL; ++s) z.Z[j][s] += lj * (z.dy[s] * H);
+        for (int s = 0; s < RPL; ++s) {
+            const double u = z.Z[j][s] + lj * (z.dy[s] * H);
+            z.Z[j][s] = in ? u : z.Z[j][s];
         }
     }
     if constexpr (VC) {
