@@ -136,7 +136,7 @@ typedef struct {
                             v_mfma_f32_16x16x4f32).  It needs ZB_MIXED, ZB_JAC_EVERY_STEP and a
                             BDF integrator (else ZB_EINVAL).  It applies to networks of 33 to 48
                             variables on 64 lanes per zone; other mappings keep ZB_LU_VALU.  On
-                            MI355X it is slower than ZB_LU_VALU at these sizes. */
+                            MI355X the two run within 2 % of each other at these sizes. */
 } zb_opts;
 
 /* Create a context on HIP device `device` (allocates a small device workspace). */

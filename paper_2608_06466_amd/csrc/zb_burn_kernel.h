@@ -798,14 +798,14 @@ __device__ __forceinline__ void lu_factor_blocked(const Ctx &c, Zone<NVP, L, LT>
     z.pivlane = lane;
     sfor<0, NVP / PB>([&](auto P) {
         constexpr int c0 = P * PB;
-        sfor<0, PB>([&](auto KK) {
+        // nv is tested once per 8 steps, as in lu_factor (steps past nv pivot identity rows)
+        auto elim = [&](auto KK) {
             constexpr int k = c0 + KK;
-            if (k >= nv) return;
             LT bv = LT(-1);
             int bi = 1 << 20;
             {
                 const LT a = fabs(z.M[0][k]);
-                if (z.pstep[0] > k && lane < nv && a > bv) {
+                if (z.pstep[0] > k && lane < NVP && a > bv) {
                     bv = a;
                     bi = lane;
                 }
@@ -827,6 +827,9 @@ __device__ __forceinline__ void lu_factor_blocked(const Ctx &c, Zone<NVP, L, LT>
                 z.M[0][J] = fma(-l, lane_read(z.M[0][J], pp), z.M[0][J]);
             });
             if (lane == k) z.pivlane = p;
+        };
+        sfor<0, PB / 8>([&](auto H) {
+            if (c0 + 8 * H < nv) sfor<8 * H, 8 * H + 8>(elim);
         });
         if constexpr (c0 + PB < NVP) {
             constexpr int NT = NVP - c0 - PB;         // columns right of the panel = rows left
