@@ -48,7 +48,9 @@ typedef enum {
     ZB_ZONE_CONV = 3,       /* ten consecutive Newton failures */
     ZB_ZONE_HMIN = 4,       /* step size fell below the resolution of t */
     ZB_ZONE_NONFINITE = 5,  /* non-finite initial state or right-hand side */
-    ZB_ZONE_OK_RETRY = 6    /* failed, then reached dt on the zone-by-zone retry (valid result) */
+    ZB_ZONE_OK_RETRY = 6,   /* failed, then reached dt on the zone-by-zone retry (valid result) */
+    ZB_ZONE_OK_FP64 = 7     /* failed in mixed precision, then reached dt in FP64 (the
+                               zb_opts.fp64_fallback run; valid result) */
 } zb_zone_status;
 
 /* Per-zone counters: accepted steps, RHS evaluations, Jacobians, LU factorizations,
@@ -137,6 +139,14 @@ typedef struct {
                             BDF integrator (else ZB_EINVAL).  It applies to networks of 33 to 48
                             variables on 64 lanes per zone; other mappings keep ZB_LU_VALU.  On
                             MI355X the two run within 2 % of each other at these sizes. */
+    int32_t fp64_fallback;   /* 1: with ZB_MIXED, a zone that fails (after the retry, if on) is
+                            burned again from its input in FP64, by the FP64 kernel of its
+                            class after the mixed-precision run, with the same options; success
+                            reports ZB_ZONE_OK_FP64, a failure that run's status, and the
+                            counters add up over both runs.  At most 1024 zones of each segment
+                            of a call fall back (the others keep their failure status), and at
+                            most 16 calls with the fallback may be in flight on one context.
+                            Ignored with ZB_FP64; ZB_EUNSUPPORTED in the server.  0: off. */
 } zb_opts;
 
 /* Create a context on HIP device `device` (allocates a small device workspace). */

@@ -1744,11 +1744,50 @@ __device__ __forceinline__ int zone_attempt_rkc(const Ctx &c, Zone<NVP, L, LT> &
     return RUNNING;
 }
 
+// The zone's counters, plus those of its first run while it is retried (in LDS) and, in the
+// FP64 run of the fallback, those its mixed-precision run left in the stats row.
+template <int NVP, int L, class LT>
+__device__ __forceinline__ void write_stats(const Ctx &c, const Zone<NVP, L, LT> &z, bool add_row)
+{
+    int32_t *o = c.stats + c.zone * 7;
+    int add[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (z.tries > 0) {
+        const int *cnt = (const int *)(c.S + c.lay.cnt);
+        for (int k = 0; k < 7; ++k) add[k] = cnt[k];
+    }
+    if (add_row)
+        for (int k = 0; k < 7; ++k) add[k] += o[k];
+    o[0] = z.nst + add[0]; o[1] = z.nfe + add[1]; o[2] = z.nje + add[2]; o[3] = z.nlu + add[3];
+    o[4] = z.nni + add[4]; o[5] = z.netf + add[5]; o[6] = z.ncf + add[6];
+}
+
+// Mixed-precision run with the FP64 fallback: a failed zone goes on its segment's list for
+// the FP64 run, with its input row left as it is (results are written only when a zone ends)
+// and its counters left in the stats row for that run to add.  False when the list is full;
+// the zone then ends with its failure.
+template <int NVP, int L, class LT>
+__device__ __forceinline__ bool zone_defer(const Ctx &c, const Zone<NVP, L, LT> &z, int seg,
+                                           const BurnArgs &A)
+{
+    const int lane = threadIdx.x & 63;
+    unsigned long long idx = 0;
+    if (c.gl == 0) idx = atomicAdd(A.fb + seg, 1ull);
+    idx = (unsigned long long)__shfl((long long)idx, lane - c.gl, 64);
+    if (idx >= (unsigned long long)FB_CAP) return false;
+    if (c.gl == 0) {
+        A.fb[MAXSEG + seg * FB_CAP + idx] = (unsigned long long)c.zone;
+        if (c.stats) write_stats(c, z, false);
+    }
+    return true;
+}
+
 template <int NVP, int L, class LT>
 __device__ __forceinline__ void zone_finish(const Ctx &c, Zone<NVP, L, LT> &z, int status, const BurnArgs &A)
 {
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
     const int ns = c.net.ns;
+    const bool replay = A.fb_mode == 2;
+    if (replay && (status == ZB_ZONE_OK || status == ZB_ZONE_OK_RETRY)) status = ZB_ZONE_OK_FP64;
     if (status != ZB_ZONE_NONFINITE) {
         double *row = c.state + c.zone * (ns + 1);
 #pragma unroll
@@ -1759,17 +1798,9 @@ __device__ __forceinline__ void zone_finish(const Ctx &c, Zone<NVP, L, LT> &z, i
     }
     if (c.gl == 0) {
         if (c.status) c.status[c.zone] = status;
-        if (c.stats) {
-            int32_t *o = c.stats + c.zone * 7;
-            int add[7] = {0, 0, 0, 0, 0, 0, 0};
-            if (z.tries > 0) {
-                const int *cnt = (const int *)(c.S + c.lay.cnt);
-                for (int k = 0; k < 7; ++k) add[k] = cnt[k];
-            }
-            o[0] = z.nst + add[0]; o[1] = z.nfe + add[1]; o[2] = z.nje + add[2]; o[3] = z.nlu + add[3];
-            o[4] = z.nni + add[4]; o[5] = z.netf + add[5]; o[6] = z.ncf + add[6];
-        }
-        if (status != ZB_ZONE_OK && status != ZB_ZONE_OK_RETRY) atomicAdd(A.nfail, 1ull);
+        if (c.stats) write_stats(c, z, replay);
+        if (status != ZB_ZONE_OK && status != ZB_ZONE_OK_RETRY && status != ZB_ZONE_OK_FP64)
+            atomicAdd(A.nfail, 1ull);
     }
 }
 
@@ -1858,7 +1889,16 @@ void burn_kernel(BurnArgs A)
                          // factors live across steps, which costs registers)
     load_segment(c, A, seg, NVP, L, RPL, method_vc(JP), jac_f32(NVP, sizeof(LT) == 4));
     c.S = smem + g * c.lay.total;
-    int64_t zones = uniform(A.seg[0].zones);
+    // zones of a segment: its own, or in the FP64 run of the fallback those on its list
+    auto seg_zones = [&](int sg) -> int64_t {
+        const BurnArgs *pa = (const BurnArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+        if (A.fb_mode == 2) {
+            const unsigned long long n = pa->fb[sg];
+            return (int64_t)(n < (unsigned long long)FB_CAP ? n : (unsigned long long)FB_CAP);
+        }
+        return pa->seg[sg].zones;
+    };
+    int64_t zones = uniform(seg_zones(0));
     bool need = true, dry = false;
     for (;;) {
         if (need && !dry) {
@@ -1868,7 +1908,7 @@ void burn_kernel(BurnArgs A)
             if (item >= (unsigned long long)zones) {
                 dry = true;
             } else {
-                c.zone = (int64_t)item;
+                c.zone = A.fb_mode == 2 ? (int64_t)A.fb[MAXSEG + seg * FB_CAP + item] : (int64_t)item;
                 z.rtol = c.rtol;
                 z.atol = c.atol;
                 z.max_steps = A.max_steps;
@@ -1885,10 +1925,7 @@ void burn_kernel(BurnArgs A)
             if (++seg >= A.nseg) break;
             load_segment(c, A, seg, NVP, L, RPL, method_vc(JP), jac_f32(NVP, sizeof(LT) == 4));
             c.S = smem + g * c.lay.total;
-            {
-                const BurnArgs *pa = (const BurnArgs *)__builtin_amdgcn_kernarg_segment_ptr();
-                zones = uniform(pa->seg[__builtin_amdgcn_readfirstlane(seg)].zones);
-            }
+            zones = uniform(seg_zones(__builtin_amdgcn_readfirstlane(seg)));
             need = true;
             dry = false;
             continue;
@@ -1914,6 +1951,11 @@ void burn_kernel(BurnArgs A)
                     if (st == RUNNING) continue;
                 } else if (st == ZB_ZONE_OK && z.tries > 0) {
                     st = ZB_ZONE_OK_RETRY;
+                }
+                if (A.fb_mode == 1 && st != ZB_ZONE_OK && st != ZB_ZONE_OK_RETRY &&
+                    zone_defer(c, z, seg, A)) {
+                    need = true;
+                    continue;
                 }
                 zone_finish(c, z, st, A);
                 need = true;

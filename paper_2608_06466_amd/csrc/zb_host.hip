@@ -52,9 +52,16 @@ extern "C" zb_err zb_context_create(int device, zb_context **out)
         delete c;
         return fail(ZB_ENOMEM, "workspace allocation failed");
     }
+    if (hipMalloc((void **)&c->fb, sizeof(unsigned long long) * FB_SLOTS * (size_t)FB_STRIDE) !=
+        hipSuccess) {
+        (void)hipFree(c->ws);
+        delete c;
+        return fail(ZB_ENOMEM, "workspace allocation failed");
+    }
     if (launch_reset(c->ws, 1 + QUEUE_SLOTS * MAXSEG, nullptr) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         (void)hipFree(c->ws);
+        (void)hipFree(c->fb);
         delete c;
         return fail(ZB_EDEVICE, "workspace initialisation failed");
     }
@@ -69,6 +76,7 @@ extern "C" zb_err zb_context_destroy(zb_context *ctx)
         DeviceGuard g(ctx->device);
         (void)hipDeviceSynchronize();
         (void)hipFree(ctx->ws);
+        (void)hipFree(ctx->fb);
         for (auto s : ctx->side) (void)hipStreamDestroy(s);
         for (auto e : ctx->join) (void)hipEventDestroy(e);
         if (ctx->fork) (void)hipEventDestroy(ctx->fork);
@@ -321,14 +329,16 @@ namespace {
 struct RunOpts {
     int max_steps, retry, retry_max_steps, jac_policy, retry_jac;
     double retry_rtol, retry_atol;
+    int fallback;
 };
 }  // namespace
 
 static RunOpts run_opts(const zb_opts *o)
 {
-    RunOpts r{100000, 0, 100000, 0, 0, 0.0, 0.0};
+    RunOpts r{100000, 0, 100000, 0, 0, 0.0, 0.0, 0};
     if (o && o->max_steps > 0) r.max_steps = o->max_steps;
     if (o) r.jac_policy = o->jac_policy;
+    if (o) r.fallback = o->fp64_fallback;
     if (o && o->retry) {
         r.retry = 1;
         r.retry_rtol = o->retry_rtol;
@@ -339,9 +349,11 @@ static RunOpts run_opts(const zb_opts *o)
     return r;
 }
 
+// With the FP64 fallback (a mixed-precision kernel and fb lists): the mixed run lists the
+// zones it fails, and the FP64 kernel of the same class then burns those from their inputs.
 static zb_err launch_segments(zb_context *ctx, const KernelInfo *k, const zb_segment *segs, int n,
                               const RunOpts &ro, hipStream_t stream, unsigned long long *queue,
-                              unsigned long long *nfail, float *ms_out)
+                              unsigned long long *nfail, float *ms_out, unsigned long long *fb)
 {
     BurnArgs A;
     memset(&A, 0, sizeof A);
@@ -374,6 +386,9 @@ static zb_err launch_segments(zb_context *ctx, const KernelInfo *k, const zb_seg
     A.retry_atol = ro.retry_atol;
     A.retry_jac = ro.retry_jac;
     A.rates_lds = rates ? 1 : 0;
+    const bool fb_on = ro.fallback && k->mixed && fb;
+    A.fb = fb;
+    A.fb_mode = fb_on ? 1 : 0;
     A.queue = queue;
     A.nfail = nfail;
 
@@ -386,6 +401,7 @@ static zb_err launch_segments(zb_context *ctx, const KernelInfo *k, const zb_seg
     int64_t groups = (total + G - 1) / G;
     int64_t blocks = std::min<int64_t>((int64_t)per_cu * ctx->cus, groups);
     HIP_TRY(launch_reset(A.queue, MAXSEG, stream));
+    if (fb_on) HIP_TRY(launch_reset(fb, MAXSEG, stream));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ms_out) {
         HIP_TRY(hipEventCreate(&e0));
@@ -394,6 +410,24 @@ static zb_err launch_segments(zb_context *ctx, const KernelInfo *k, const zb_seg
     }
     void *args[] = {&A};
     HIP_TRY(hipLaunchKernel(k->fn, dim3((unsigned)blocks), dim3(64), args, lds, stream));
+    if (fb_on) {
+        // the FP64 kernel of the class (the blocked-LU methods have none: their vector-LU form)
+        const KernelInfo *kf = kernel_for(k->nvp, k->lanes, 0, k->jac);
+        if (!kf) return fail(ZB_EUNSUPPORTED, "no FP64 kernel for the fallback (nvp %d)", k->nvp);
+        const size_t ldsf = launch_lds(kf, max_nr, rates);
+        int per_cu_f = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_f, kf->fn, 64, ldsf));
+        if (per_cu_f < 1 || ldsf > 160 * 1024)
+            return fail(ZB_EUNSUPPORTED, "fallback kernel does not fit on a CU (LDS %zu)", ldsf);
+        const int Gf = 64 / kf->lanes;
+        const int64_t listed = std::min<int64_t>(total, (int64_t)n * FB_CAP);
+        const int64_t blocks_f = std::min<int64_t>((int64_t)per_cu_f * ctx->cus, (listed + Gf - 1) / Gf);
+        BurnArgs B = A;
+        B.fb_mode = 2;
+        void *bargs[] = {&B};
+        HIP_TRY(launch_reset(A.queue, MAXSEG, stream));
+        HIP_TRY(hipLaunchKernel(kf->fn, dim3((unsigned)blocks_f), dim3(64), bargs, ldsf, stream));
+    }
     if (ms_out) {
         HIP_TRY(hipEventRecord(e1, stream));
         HIP_TRY(hipEventSynchronize(e1));
@@ -442,6 +476,8 @@ static zb_err plan_groups(zb_context *ctx, const zb_segment *segs, int n, const 
         const zb_err e = check_lu(opts, prec);
         if (e != ZB_OK) return e;
     }
+    if (opts && opts->fp64_fallback != 0 && opts->fp64_fallback != 1)
+        return fail(ZB_EINVAL, "fp64_fallback %d", opts->fp64_fallback);
     const int jac = method_of(opts);
     for (int i = 0; i < n; ++i) {
         zb_err e = check_segment(ctx, segs[i]);
@@ -506,21 +542,29 @@ zb_err zbh::burn_impl(zb_context *ctx, const zb_segment *segs, int n, const zb_o
     if (ws && ng > ws->launches)
         return fail(ZB_EINVAL, "workspace holds queues for %d launches, %d needed", ws->launches, ng);
     DeviceGuard g(ctx->device);
-    std::vector<unsigned long long *> queue(ng);
+    std::vector<unsigned long long *> queue(ng), fb(ng, nullptr);
     unsigned long long *nfail = ws ? ws->nfail : ctx->ws;
+    const bool want_fb = ro.fallback && opts->precision == ZB_MIXED;
     if (ws) {
         for (int i = 0; i < ng; ++i) queue[i] = ws->queue + (size_t)i * MAXSEG;
+        if (want_fb && !ws->fb) return fail(ZB_EUNSUPPORTED, "this caller has no FP64 fallback lists");
+        if (want_fb)
+            for (int i = 0; i < ng; ++i) fb[i] = ws->fb + (size_t)i * FB_STRIDE;
     } else {
         std::lock_guard<std::mutex> lk(ctx->mu);
         for (int i = 0; i < ng; ++i) {
             queue[i] = ctx->ws + 1 + (size_t)ctx->next_slot * MAXSEG;
             ctx->next_slot = (ctx->next_slot + 1) % QUEUE_SLOTS;
+            if (want_fb) {
+                fb[i] = ctx->fb + (size_t)ctx->next_fb * FB_STRIDE;
+                ctx->next_fb = (ctx->next_fb + 1) % FB_SLOTS;
+            }
         }
     }
     hipStream_t s0 = (hipStream_t)stream;
     if (ng == 1)
         return launch_segments(ctx, groups[0].k, groups[0].segs.data(), (int)groups[0].segs.size(),
-                               ro, s0, queue[0], nfail, ms_out);
+                               ro, s0, queue[0], nfail, ms_out, fb[0]);
     // Several kernel classes: the costliest runs on the caller's stream and the
     // others on side streams forked from it and joined back, so the classes share
     // the GPU (a class's tail is filled by the others) instead of running in turn.
@@ -533,7 +577,7 @@ zb_err zbh::burn_impl(zb_context *ctx, const zb_segment *segs, int n, const zb_o
     for (int i = 0; i < ng; ++i) {
         hipStream_t s = i == 0 ? s0 : ctx->side[(i - 1) % nside];
         e = launch_segments(ctx, groups[i].k, groups[i].segs.data(), (int)groups[i].segs.size(),
-                            ro, s, queue[i], nfail, nullptr);
+                            ro, s, queue[i], nfail, nullptr, fb[i]);
         if (e != ZB_OK) return e;
     }
     for (int j = 0; j < nside; ++j) {
@@ -589,6 +633,7 @@ struct zb_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     unsigned long long *queues = nullptr;   // launches x MAXSEG, private to this graph
+    unsigned long long *fb = nullptr;       // launches x FB_STRIDE with the FP64 fallback
 };
 
 extern "C" zb_err zb_graph_create(zb_context *ctx, const zb_segment *segs, int32_t n_seg,
@@ -614,7 +659,15 @@ extern "C" zb_err zb_graph_create(zb_context *ctx, const zb_segment *segs, int32
         delete G;
         return fail(ZB_EDEVICE, "stream creation failed");
     }
-    Workspace ws{G->queues, std::max(launches, 1), ctx->ws};
+    if (opts && opts->fp64_fallback && opts->precision == ZB_MIXED &&
+        hipMalloc((void **)&G->fb, sizeof(unsigned long long) * FB_STRIDE * (size_t)std::max(launches, 1)) !=
+            hipSuccess) {
+        (void)hipStreamDestroy(s);
+        (void)hipFree(G->queues);
+        delete G;
+        return fail(ZB_ENOMEM, "graph fallback-list allocation failed");
+    }
+    Workspace ws{G->queues, std::max(launches, 1), ctx->ws, G->fb};
     e = ZB_OK;
     if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         e = fail(ZB_EDEVICE, "hipStreamBeginCapture failed");
@@ -655,6 +708,7 @@ extern "C" zb_err zb_graph_destroy(zb_graph *G)
         if (G->exec) (void)hipGraphExecDestroy(G->exec);
         if (G->graph) (void)hipGraphDestroy(G->graph);
         (void)hipFree(G->queues);
+        (void)hipFree(G->fb);
     }
     delete G;
     return ZB_OK;

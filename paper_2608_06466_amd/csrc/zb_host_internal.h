@@ -46,7 +46,12 @@ struct Workspace {
     unsigned long long *queue;   // launches x MAXSEG
     int launches;
     unsigned long long *nfail;
+    unsigned long long *fb;      // launches x FB_STRIDE FP64 fallback lists (nullptr: none)
 };
+
+// FP64 fallback lists of a context: calls with the fallback take them in turn, so at most
+// this many such calls may be in flight on one context at a time.
+constexpr int FB_SLOTS = 16;
 
 const zb::KernelInfo *find_kernel(int nv, int lanes, int mixed, int jac);
 const zb::KernelInfo *kernel_for(int nv, int lanes, int mixed, int method);
@@ -81,6 +86,8 @@ struct zb_context {
     int cus = 0;
     unsigned long long *ws = nullptr;   // [0] failed zones, then QUEUE_SLOTS x MAXSEG queue counters
     int next_slot = 0;
+    unsigned long long *fb = nullptr;   // FB_SLOTS x FB_STRIDE FP64 fallback lists
+    int next_fb = 0;
     std::mutex mu;
     // autotuned lanes per zone, keyed by (nv, nr, precision)
     struct Tuned { int nv, nr, prec, lanes; };

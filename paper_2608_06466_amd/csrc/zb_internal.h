@@ -56,7 +56,15 @@ struct BurnArgs {
     unsigned long long *nfail;     // zones that ended with a non-OK status
     int rates_lds;                 // 1: per-reaction rate factors kept in LDS (some segment
                                    // has rate scales or a network without temperature)
+    unsigned long long *fb;        // FP64 fallback: MAXSEG counters, then MAXSEG x FB_CAP zones
+    int fb_mode;                   // 0 off; 1 the mixed run lists its failed zones;
+                                   // 2 the FP64 run burns the listed zones
 };
+
+// FP64 fallback lists: zones per segment and launch (further failed zones keep their
+// mixed-precision status), and the device words of one launch's lists.
+constexpr int FB_CAP = 1024;
+constexpr int FB_STRIDE = MAXSEG * (1 + FB_CAP);
 
 // Kernel methods (a template parameter of the burn kernel, KernelInfo.jac on the host):
 // fixed-coefficient BDF with the Jacobian every step or reused, RKC, the same two for the

@@ -401,6 +401,10 @@ extern "C" zb_err zb_server_create(zb_context *ctx, const zb_server_opts *so, zb
         const zb_err e = check_lu(&bo, bo.precision);
         if (e != ZB_OK) return e;
     }
+    if (bo.fp64_fallback != 0 && bo.fp64_fallback != 1)
+        return fail(ZB_EINVAL, "fp64_fallback %d", bo.fp64_fallback);
+    if (bo.fp64_fallback && bo.precision == ZB_MIXED)
+        return fail(ZB_EUNSUPPORTED, "the server has no FP64 fallback");
     DeviceGuard g(ctx->device);
     zb_server *S = new (std::nothrow) zb_server();
     if (!S) return fail(ZB_ENOMEM, "host allocation failed");
@@ -563,7 +567,8 @@ extern "C" zb_err zb_server_fetch(zb_server *S, uint64_t ticket, double *host_st
         info->zones = z;
         int64_t ok = 0;
         if (e == ZB_OK)
-            for (int64_t i = 0; i < z; ++i) ok += st_dst[i] == ZB_ZONE_OK || st_dst[i] == ZB_ZONE_OK_RETRY;
+            for (int64_t i = 0; i < z; ++i)
+                ok += st_dst[i] == ZB_ZONE_OK || st_dst[i] == ZB_ZONE_OK_RETRY || st_dst[i] == ZB_ZONE_OK_FP64;
         info->zones_ok = ok;
         info->queue_s = r->t_admit - r->t_submit;
         info->latency_s = r->t_done - r->t_submit;

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libzoneburn.so")
 OK, EINVAL, ENOMEM, EDEVICE, EZONES, EBUSY, ENOTFOUND, EUNSUPPORTED = range(8)
 FP64, MIXED = 0, 1
 ZONE_STATUS = {0: "OK", 1: "MAXSTEPS", 2: "ERRTEST", 3: "CONV", 4: "HMIN", 5: "NONFINITE",
-               6: "OK_RETRY"}
+               6: "OK_RETRY", 7: "OK_FP64"}
 STAT_FIELDS = ("nst", "nfe", "nje", "nlu", "nni", "netf", "ncf")
 
 
@@ -40,7 +40,8 @@ class _Opts(C.Structure):
     _fields_ = [("max_steps", C.c_int32), ("precision", C.c_int32), ("mapping", C.c_int32),
                 ("retry", C.c_int32), ("retry_rtol", C.c_double), ("retry_atol", C.c_double),
                 ("retry_max_steps", C.c_int32), ("jac_policy", C.c_int32),
-                ("integrator", C.c_int32), ("retry_jac", C.c_int32), ("lu", C.c_int32)]
+                ("integrator", C.c_int32), ("retry_jac", C.c_int32), ("lu", C.c_int32),
+                ("fp64_fallback", C.c_int32)]
 
 
 class _Segment(C.Structure):
@@ -184,12 +185,14 @@ JAC_EVERY_STEP, JAC_REUSE = 0, 1
 BDF, RKC = 0, 1
 
 
-def _opts(precision, lanes, max_steps, retry=None, jac_policy=0, integrator=0, lu="valu"):
+def _opts(precision, lanes, max_steps, retry=None, jac_policy=0, integrator=0, lu="valu",
+          fp64_fallback=False):
     """retry: None, or (rtol, atol, max_steps[, jac]) of the zone-by-zone retry of failed
     zones, jac "analytic" (default) or "fd" (finite-difference Jacobian in the retry).
     jac_policy: 0 Jacobian and LU every step attempt, 1 VODE-style reuse.
     integrator: "bdf" (0), "rkc" (1) or "bdf_variable" (2, VODE's variable-coefficient form).
-    lu: "valu" (0) or "mfma" (1, the blocked FP32 LU on the matrix cores; 48-row kernels)."""
+    lu: "valu" (0) or "mfma" (1, the blocked FP32 LU on the matrix cores; 48-row kernels).
+    fp64_fallback: mixed precision only; zones that fail are burned again in FP64."""
     prec = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}[precision]
     jp = {"every_step": 0, "reuse": 1, 0: 0, 1: 1}[jac_policy]
     it = {"bdf": 0, "rkc": 1, "bdf_variable": 2, 0: 0, 1: 1, 2: 2}[integrator]
@@ -197,13 +200,14 @@ def _opts(precision, lanes, max_steps, retry=None, jac_policy=0, integrator=0, l
     if lv is None:
         raise ValueError("lu must be 'valu' or 'mfma'")
     if retry is None:
-        return _Opts(int(max_steps or 0), prec, int(lanes or 0), 0, 0.0, 0.0, 0, jp, it, 0, lv)
+        return _Opts(int(max_steps or 0), prec, int(lanes or 0), 0, 0.0, 0.0, 0, jp, it, 0, lv,
+                     int(bool(fp64_fallback)))
     rjac = retry[3] if len(retry) > 3 else "analytic"
     rj = {"analytic": 0, "fd": 1, 0: 0, 1: 1}.get(rjac)
     if rj is None:
         raise ValueError("retry jac must be 'analytic' or 'fd'")
     return _Opts(int(max_steps or 0), prec, int(lanes or 0), 1, float(retry[0]), float(retry[1]),
-                 int(retry[2]), jp, it, rj, lv)
+                 int(retry[2]), jp, it, rj, lv, int(bool(fp64_fallback)))
 
 
 def _check_state(net, state):
@@ -215,7 +219,7 @@ def _check_state(net, state):
 
 def burn(ctx, net, state, dt, rtol, atol, rate_scale=None, precision="fp64", lanes=0,
          max_steps=0, want_status=True, want_stats=True, stream=None, source=None, retry=None,
-         jac_policy=0, integrator="bdf", lu="valu"):
+         jac_policy=0, integrator="bdf", lu="valu", fp64_fallback=False):
     """In-place burn of state [zones][ns+1]; returns (status int32[zones], stats int32[zones,7]).
 
     source: optional constant per-zone term [zones][ns+1] added to the right-hand side
@@ -229,7 +233,8 @@ def burn(ctx, net, state, dt, rtol, atol, rate_scale=None, precision="fp64", lan
         burn_batch(ctx, [dict(net=net, state=state, dt=dt, rtol=rtol, atol=atol, rate_scale=rate_scale,
                               status=status, stats=stats, source=source)],
                    precision=precision, lanes=lanes, max_steps=max_steps, stream=stream, retry=retry,
-                   jac_policy=jac_policy, integrator=integrator, lu=lu)
+                   jac_policy=jac_policy, integrator=integrator, lu=lu,
+                   fp64_fallback=fp64_fallback)
         return status, stats
     zones = state.shape[0]
     if rate_scale is not None and (rate_scale.dtype != torch.float64 or not rate_scale.is_cuda
@@ -238,7 +243,7 @@ def burn(ctx, net, state, dt, rtol, atol, rate_scale=None, precision="fp64", lan
         raise ValueError("rate_scale must be a contiguous float64 CUDA tensor [zones][R]")
     status = torch.empty(zones, dtype=torch.int32, device=state.device) if want_status else None
     stats = torch.empty((zones, 7), dtype=torch.int32, device=state.device) if want_stats else None
-    o = _opts(precision, lanes, max_steps, retry, jac_policy, integrator, lu)
+    o = _opts(precision, lanes, max_steps, retry, jac_policy, integrator, lu, fp64_fallback)
     _check(lib().zb_burn(ctx.h, net.h, _ptr(state), zones, float(dt), float(rtol), float(atol),
                          _ptr(rate_scale), C.byref(o), _ptr(status), _ptr(stats),
                          _stream_handle(stream)), "zb_burn")
@@ -269,11 +274,11 @@ def _segments(segments):
 
 
 def burn_batch(ctx, segments, precision="fp64", lanes=0, max_steps=0, stream=None, retry=None,
-               jac_policy=0, integrator="bdf", lu="valu"):
+               jac_policy=0, integrator="bdf", lu="valu", fp64_fallback=False):
     """segments: list of dicts(net, state, dt, rtol, atol, rate_scale=None, status=None,
     stats=None, source=None); retry: None or (rtol, atol, max_steps[, jac])."""
     arr = _segments(segments)
-    o = _opts(precision, lanes, max_steps, retry, jac_policy, integrator, lu)
+    o = _opts(precision, lanes, max_steps, retry, jac_policy, integrator, lu, fp64_fallback)
     _check(lib().zb_burn_batch(ctx.h, arr, len(segments), C.byref(o), _stream_handle(stream)),
            "zb_burn_batch")
 
@@ -282,11 +287,11 @@ class Graph:
     """A burn of fixed buffers captured once as a HIP graph (zb_graph_*); launch() replays it."""
 
     def __init__(self, ctx, segments, precision="fp64", lanes=0, max_steps=0, retry=None,
-                 jac_policy=0, integrator="bdf", lu="valu"):
+                 jac_policy=0, integrator="bdf", lu="valu", fp64_fallback=False):
         self.ctx = ctx
         self._segs = segments          # the buffers must outlive the graph
         arr = _segments(segments)
-        o = _opts(precision, lanes, max_steps, retry, jac_policy, integrator, lu)
+        o = _opts(precision, lanes, max_steps, retry, jac_policy, integrator, lu, fp64_fallback)
         h = C.c_void_p()
         _check(lib().zb_graph_create(ctx.h, arr, len(segments), C.byref(o), C.byref(h)),
                "zb_graph_create")
@@ -312,11 +317,12 @@ class Server:
 
     def __init__(self, ctx, hbm_budget_bytes, precision="fp64", lanes=0, max_steps=0, streams=0,
                  launches_per_stream=0, slice_zones=0, max_pending=0, retry=None, jac_policy=0,
-                 integrator="bdf", lu="valu"):
+                 integrator="bdf", lu="valu", fp64_fallback=False):
         self.ctx = ctx
         o = _ServerOpts(int(hbm_budget_bytes), int(streams), int(launches_per_stream),
                         int(slice_zones), int(max_pending), 0,
-                        _opts(precision, lanes, max_steps, retry, jac_policy, integrator, lu))
+                        _opts(precision, lanes, max_steps, retry, jac_policy, integrator, lu,
+                              fp64_fallback))
         h = C.c_void_p()
         _check(lib().zb_server_create(ctx.h, C.byref(o), C.byref(h)), "zb_server_create")
         self.h = h

@@ -753,3 +753,71 @@ def test_fp64_whole_wave_rate_factors(zbm):
         assert np.array_equal(status[k].cpu().numpy(), single[name][1]), name
         assert np.array_equal(stats[k].cpu().numpy(), single[name][2]), name
     net.close()
+
+
+def test_fp64_fallback(zbm):
+    """fp64_fallback with the mixed precision: zones that fail in mixed precision are burned
+    again from their inputs by the FP64 kernel.  Such a zone reports OK_FP64 (7), its row is
+    bitwise the plain FP64 burn's, and its counters are the sum of both runs; every other zone
+    is bitwise the plain mixed burn's.  The same holds for a two-segment batch (one list per
+    segment) and for a graph replay; the server rejects the option."""
+    zb, ctx = zbm
+    net_d = W.random_network(7, 12, 881)
+    full = W.random_zones(net_d, 131072, seed=882)
+    net = zb.Network(ctx, net_d)
+
+    def run(st, **kw):
+        t = torch.tensor(st, device="cuda:0")
+        status, stats = zb.burn(ctx, net, t, 1.0, 1e-8, 1e-12, **kw)
+        zb.sync(ctx)
+        return t.cpu().numpy(), status.cpu().numpy(), stats.cpu().numpy()
+
+    failed = np.nonzero(run(full, precision="mixed")[1] != 0)[0]
+    assert failed.size > 0, "the input must have zones that fail in mixed precision"
+    idx = np.union1d(failed, np.arange(251))
+    st = full[idx]
+    mixed = run(st, precision="mixed")
+    fp64 = run(st, precision="fp64")
+    fb = run(st, precision="mixed", fp64_fallback=True)
+    bad = mixed[1] != 0
+    assert bad.sum() == failed.size
+    assert np.all(fp64[1][bad] == 0)
+    assert np.all(fb[1][bad] == 7) and np.all(fb[1][~bad] == mixed[1][~bad])
+    assert np.array_equal(fb[0][bad], fp64[0][bad]) and np.array_equal(fb[0][~bad], mixed[0][~bad])
+    assert np.array_equal(fb[2][bad], mixed[2][bad] + fp64[2][bad])
+    assert np.array_equal(fb[2][~bad], mixed[2][~bad])
+    # the rescued zones against the oracle (status 7 counts as OK there)
+    nv = net_d["n_species"] + net_d["thermal"]
+    ref = oracle_ref(net_d, st[bad], 1.0, 1e-8, 1e-12)
+    gfine = run_gpu(zb, ctx, net_d, st[bad], 1.0, 1e-10, 1e-14, precision="fp64",
+                    max_steps=10000000, net=net)
+    rescued = (fb[0][bad], np.where(fb[1][bad] == 7, 0, fb[1][bad]).astype(np.int32), fb[2][bad])
+    check("fp64 fallback zones", rescued, ref, 1e-8, 1e-12, nv, gfine)
+    # two segments in one call: one list each
+    half = len(idx) // 2
+    ts = [torch.tensor(st[:half], device="cuda:0"), torch.tensor(st[half:], device="cuda:0")]
+    status = [torch.empty(t.shape[0], dtype=torch.int32, device="cuda:0") for t in ts]
+    stats = [torch.empty((t.shape[0], 7), dtype=torch.int32, device="cuda:0") for t in ts]
+    zb.burn_batch(ctx, [dict(net=net, state=ts[k], dt=1.0, rtol=1e-8, atol=1e-12, status=status[k],
+                             stats=stats[k]) for k in range(2)], precision="mixed", fp64_fallback=True)
+    zb.sync(ctx)
+    got = [np.concatenate([a.cpu().numpy() for a in x]) for x in (ts, status, stats)]
+    for a, b in zip(got, fb):
+        assert np.array_equal(a, b)
+    # a graph replay
+    tg = torch.tensor(st, device="cuda:0")
+    sg = torch.empty(len(idx), dtype=torch.int32, device="cuda:0")
+    gs = torch.empty((len(idx), 7), dtype=torch.int32, device="cuda:0")
+    g = zb.Graph(ctx, [dict(net=net, state=tg, dt=1.0, rtol=1e-8, atol=1e-12, status=sg, stats=gs)],
+                 precision="mixed", fp64_fallback=True)
+    for _ in range(2):
+        tg.copy_(torch.tensor(st, device="cuda:0"))
+        g.launch()
+        zb.sync(ctx)
+        assert np.array_equal(tg.cpu().numpy(), fb[0]) and np.array_equal(sg.cpu().numpy(), fb[1])
+        assert np.array_equal(gs.cpu().numpy(), fb[2])
+    g.close()
+    with pytest.raises(zb.ZoneburnError) as e:
+        zb.Server(ctx, 1 << 26, precision="mixed", fp64_fallback=True)
+    assert e.value.code == zb.EUNSUPPORTED
+    net.close()
