@@ -86,7 +86,7 @@ def headline(args):
         print("bench.py needs an MI355X GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
-    cfg = W.config2(args.zones or (1 << 20))
+    cfg = W.nv14(args.zones or (1 << 20))
     net_d, state0_np = cfg["net"], cfg["state"]
     dt, rtol, atol = cfg["dt"], cfg["rtol"], cfg["atol"]
     zones = state0_np.shape[0]
@@ -269,7 +269,7 @@ def robertson(args):
     import oracle
     from paper_2608_06466_amd import workloads as W
     from paper_2608_06466_amd import zoneburn as zb
-    cfg = W.config1(args.zones or 4096)
+    cfg = W.robertson(args.zones or 4096)
     zones = cfg["state"].shape[0]
     ctx = zb.Context(0)
     net = zb.Network(ctx, cfg["net"])
@@ -296,7 +296,7 @@ def robertson(args):
     st = stats.cpu().numpy()
     ok = int((status.cpu().numpy() == 0).sum())
     wall = float(np.mean(ts))
-    line = _common_line("zone-burns/s, Robertson (config 1)", round(ok / wall, 1), "zone-burns/s", args,
+    line = _common_line("zone-burns/s, Robertson (3 species, t = 0..1e5)", round(ok / wall, 1), "zone-burns/s", args,
                         round(wall * 1e3, 3), "f64",
                         {"workload": f"Robertson, {zones} zones, lognormal(0,0.1) rate scales, t=0..1e5, "
                                      "rtol=1e-8, atol=1e-12", "lanes_per_zone": best,
@@ -324,13 +324,13 @@ def robertson(args):
 
 def batched(args):
     """Four networks (nv 3, 14, 22, 48; 4:2:1:1 of 2^21 zones) in one zb_burn_batch call, FP64
-    (config 3) and with the FP32 LU (config 4), each against the oracle on a stratified sample;
+    and with the FP32 LU, each against the oracle on a stratified sample;
     the FP32 run again with the blocked matrix-core LU (lu='mfma': the 48-variable class)."""
     import torch
     import oracle
     from paper_2608_06466_amd import workloads as W
     from paper_2608_06466_amd import zoneburn as zb
-    segs_h = W.config3(args.zones or (1 << 21))
+    segs_h = W.batched(args.zones or (1 << 21))
     ctx = zb.Context(0)
     nets = [zb.Network(ctx, s["net"]) for s in segs_h]
     total = sum(s["state"].shape[0] for s in segs_h)
@@ -381,7 +381,7 @@ def batched(args):
                 "frac": round(a / FP64_PEAK_TFLOPS, 4), "traffic": None}
 
     m, f = res["mixed"], res["fp64"]
-    line = _common_line("zone-burns/s, four networks in one call (configs 3 and 4)", round(m["ok"] / m["wall_s"], 1),
+    line = _common_line("zone-burns/s, four networks (nv 3, 14, 22, 48) in one call", round(m["ok"] / m["wall_s"], 1),
                         "zone-burns/s", args, round(m["wall_s"] * 1e3, 2), "f64 (f32 LU)",
                         {"workload": f"Robertson : nv14 : nv22 : nv48 = 4:2:1:1 of {total} zones, "
                                      "T log-uniform on [90, 2500] K, dt 1 (Robertson 1e5), rtol 1e-8, "
@@ -431,14 +431,14 @@ def batched(args):
 
 
 def serving(args):
-    """Poisson stream of burn requests (1k..256k zones, the four networks of config 3, rtol 1e-6
+    """Poisson stream of burn requests (1k..256k zones, the four networks of the batched workload, rtol 1e-6
     or 1e-8) through the continuous-batching server: throughput and request latency."""
     import threading
     import torch
     from paper_2608_06466_amd import workloads as W
     from paper_2608_06466_amd import zoneburn as zb
     ctx = zb.Context(0)
-    nets_d = W.config3_networks()
+    nets_d = W.batched_networks()
     nets = [zb.Network(ctx, n) for n in nets_d]
     # capacity pilot: zone-burns/s of each network on a full GPU
     rate = []
@@ -494,7 +494,7 @@ def serving(args):
     queue = np.array([i["queue_s"] for i in infos])
     ok = sum(i["zones_ok"] for i in infos)
     zones = sum(r["zones"] for r in reqs)
-    line = _common_line("serving: zone-burns/s and request latency p50/p99 (config 5)",
+    line = _common_line("serving: zone-burns/s and request latency p50/p99 (Poisson burn requests)",
                         round(ok / (t_end - t_start), 1), "zone-burns/s", args,
                         round((t_end - t_start) * 1e3, 1), "f64 (f32 LU)" if args.precision == "mixed" else "f64",
                         {"workload": f"{args.requests} Poisson requests at {lam:.3f}/s ({args.load} of the "

@@ -156,54 +156,55 @@ def energy_test_network(ns, n_reactions, seed, B_seed=None):
 
 
 # ---------------------------------------------------------------------------
-# The five benchmark configurations (sizes as stated for the workloads).
+# The benchmark workloads: Robertson, the 14-variable network, the four-network batch
+# (the mixed-precision and serving workloads reuse these inputs).
 # ---------------------------------------------------------------------------
 
-CONFIG2_NET_SEED, CONFIG2_ZONE_SEED = 201, 202
-CONFIG3_NETS = ((13, 20, 301), (21, 50, 302), (47, 150, 303))
-CONFIG3_ZONE_SEED = 304
-CONFIG3_T_RANGE = (90.0, 2500.0)   # log-uniform; gives 7..~5000 BDF steps per zone (oracle)
+NV14_NET_SEED, NV14_ZONE_SEED = 201, 202
+BATCHED_NETS = ((13, 20, 301), (21, 50, 302), (47, 150, 303))
+BATCHED_ZONE_SEED = 304
+BATCHED_T_RANGE = (90.0, 2500.0)   # log-uniform; gives 7..~5000 BDF steps per zone (oracle)
 
 
-def config1(zones=4096):
+def robertson(zones=4096):
     """Robertson, 4096 zones, t in [0, 1e5], rtol 1e-8, atol 1e-12."""
     net = robertson_network()
     state, scale = robertson_zones(zones)
     return dict(net=net, state=state, scale=scale, dt=1.0e5, rtol=1.0e-8, atol=1.0e-12)
 
 
-def config2_network():
-    return random_network(13, 30, CONFIG2_NET_SEED)
+def nv14_network():
+    return random_network(13, 30, NV14_NET_SEED)
 
 
-def config2(zones=1 << 20):
+def nv14(zones=1 << 20):
     """13 species + T, 30 reactions, T ~ U(1e3, 5e3), Dirichlet(1) abundances, dt = 1."""
-    net = config2_network()
-    state = random_zones(net, zones, CONFIG2_ZONE_SEED)
+    net = nv14_network()
+    state = random_zones(net, zones, NV14_ZONE_SEED)
     return dict(net=net, state=state, scale=None, dt=1.0, rtol=1.0e-8, atol=1.0e-12)
 
 
-def config3_networks():
+def batched_networks():
     nets = [robertson_network()]
-    for ns, R, seed in CONFIG3_NETS:
+    for ns, R, seed in BATCHED_NETS:
         nets.append(random_network(ns, R, seed))
     return nets
 
 
-def config3(total_zones=1 << 21):
+def batched(total_zones=1 << 21):
     """Four networks (nv = 3, 14, 22, 48) in zone ratio 4:2:1:1 for one batched launch."""
-    nets = config3_networks()
+    nets = batched_networks()
     parts = [total_zones // 2, total_zones // 4, total_zones // 8, total_zones - total_zones // 2
              - total_zones // 4 - total_zones // 8]
     segs = []
-    rng_seeds = np.random.SeedSequence(CONFIG3_ZONE_SEED).spawn(4)
+    rng_seeds = np.random.SeedSequence(BATCHED_ZONE_SEED).spawn(4)
     for k, (net, nz) in enumerate(zip(nets, parts)):
         if k == 0:
             st, sc = robertson_zones(nz, seed=int(rng_seeds[0].generate_state(1)[0]))
             segs.append(dict(net=net, state=st, scale=sc, dt=1.0e5, rtol=1.0e-8, atol=1.0e-12))
         else:
             st = random_zones(net, nz, int(rng_seeds[k].generate_state(1)[0]),
-                              T_range=CONFIG3_T_RANGE, T_dist="loguniform")
+                              T_range=BATCHED_T_RANGE, T_dist="loguniform")
             segs.append(dict(net=net, state=st, scale=None, dt=1.0, rtol=1.0e-8, atol=1.0e-12))
     return segs
 
@@ -225,10 +226,10 @@ def serving_requests(n_requests, seed=501, rate_hz=100.0, size_range=(1 << 10, 1
 
 def request_inputs(nets, req):
     """(state, rate scales or None, dt) of one request drawn by serving_requests(); nets are
-    config3_networks() (0 Robertson, 1..3 the random networks of 14, 22, 48 variables)."""
+    batched_networks() (0 Robertson, 1..3 the random networks of 14, 22, 48 variables)."""
     k = req["net"]
     if k == 0:
         st, sc = robertson_zones(req["zones"], seed=req["seed"])
         return st, sc, 1.0e5
-    st = random_zones(nets[k], req["zones"], req["seed"], T_range=CONFIG3_T_RANGE, T_dist="loguniform")
+    st = random_zones(nets[k], req["zones"], req["seed"], T_range=BATCHED_T_RANGE, T_dist="loguniform")
     return st, None, 1.0

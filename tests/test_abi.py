@@ -40,10 +40,10 @@ def test_error_strings_without_device():
 def test_workload_generators_are_deterministic():
     import numpy as np
     from paper_2608_06466_amd import workloads as W
-    a, b = W.config2(64), W.config2(64)
+    a, b = W.nv14(64), W.nv14(64)
     assert np.array_equal(a["state"], b["state"])
     assert np.allclose(a["state"][:, :13].sum(1), 1.0)
-    net = W.config2_network()
+    net = W.nv14_network()
     assert net["reactant"].shape == (30, 2)
     for r in range(30):
         assert sorted(net["reactant"][r]) != sorted(net["product"][r])

@@ -117,26 +117,26 @@ def run_pair(zb, ctx, net_dict, state, dt, rtol, atol, scale=None, precision="fp
 @pytest.mark.parametrize("lanes", [1, 4])
 def test_robertson_parity(zbm, lanes):
     zb, ctx = zbm
-    c = W.config1(333)
+    c = W.robertson(333)
     ref = oracle_ref(c["net"], c["state"], c["dt"], c["rtol"], c["atol"], c["scale"])
     gpu, fine = run_pair(zb, ctx, c["net"], c["state"], c["dt"], c["rtol"], c["atol"], c["scale"], lanes=lanes)
     check(f"robertson L={lanes}", gpu, ref, c["rtol"], c["atol"], 3, fine)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_config2_parity(zbm, precision):
+def test_nv14_parity(zbm, precision):
     zb, ctx = zbm
-    c = W.config2(301)
+    c = W.nv14(301)
     ref = oracle_ref(c["net"], c["state"], c["dt"], c["rtol"], c["atol"])
     gpu, fine = run_pair(zb, ctx, c["net"], c["state"], c["dt"], c["rtol"], c["atol"], precision=precision)
-    check(f"config2 {precision}", gpu, ref, c["rtol"], c["atol"], 14, fine)
+    check(f"nv14 {precision}", gpu, ref, c["rtol"], c["atol"], 14, fine)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("k", [1, 2, 3])
-def test_config3_networks_parity(zbm, k, precision):
+def test_batched_networks_parity(zbm, k, precision):
     zb, ctx = zbm
-    ns, R, seed = W.CONFIG3_NETS[k - 1]
+    ns, R, seed = W.BATCHED_NETS[k - 1]
     net = W.random_network(ns, R, seed)
     zones = {1: 131, 2: 67, 3: 19}[k]
     st = W.random_zones(net, zones, seed=900 + k, T_range=(300.0, 6000.0), T_dist="loguniform")
@@ -162,7 +162,7 @@ def test_linear_and_two_body_networks(zbm):
 
 def test_edge_cases_and_statuses(zbm):
     zb, ctx = zbm
-    c = W.config2(40)
+    c = W.nv14(40)
     net = zb.Network(ctx, c["net"])
     # zero zones and one zone
     out, status, stats = run_gpu(zb, ctx, c["net"], c["state"][:0], 1.0, 1e-8, 1e-12, net=net)
@@ -202,7 +202,7 @@ def test_edge_cases_and_statuses(zbm):
 def test_zone_result_independent_of_batch(zbm, precision):
     """A zone burned alone, at another position, or next to other zones: bitwise the same."""
     zb, ctx = zbm
-    c = W.config2(257)
+    c = W.nv14(257)
     net = zb.Network(ctx, c["net"])
     full = run_gpu(zb, ctx, c["net"], c["state"], 1.0, 1e-8, 1e-12, precision=precision, net=net)
     idx = [0, 13, 200, 256]
@@ -215,8 +215,8 @@ def test_zone_result_independent_of_batch(zbm, precision):
 
 def test_batch_launch_matches_single_launches(zbm):
     zb, ctx = zbm
-    n2 = W.config2_network()
-    ns, R, seed = W.CONFIG3_NETS[0]
+    n2 = W.nv14_network()
+    ns, R, seed = W.BATCHED_NETS[0]
     n3 = W.random_network(ns, R, seed)
     s2 = W.random_zones(n2, 70, seed=1)
     s3 = W.random_zones(n3, 45, seed=2)
@@ -235,10 +235,10 @@ def test_batch_launch_matches_single_launches(zbm):
     N3.close()
 
 
-def test_config2_full_size_sampled(zbm):
+def test_nv14_full_size_sampled(zbm):
     """2^20 zones in the benchmark's launch configuration; 48 sampled zones against the oracle."""
     zb, ctx = zbm
-    c = W.config2()
+    c = W.nv14()
     rng = np.random.default_rng(7)
     idx = np.sort(rng.choice(c["state"].shape[0], 256, replace=False))
     ref = oracle_ref(c["net"], c["state"][idx], 1.0, 1e-8, 1e-12)
@@ -248,28 +248,28 @@ def test_config2_full_size_sampled(zbm):
     for prec in ("fp64", "mixed"):
         out, status, stats = run_gpu(zb, ctx, c["net"], c["state"], 1.0, 1e-8, 1e-12, precision=prec)
         bad = np.nonzero(status)[0]
-        print(f"config2 2^20 {prec}: failed zones {bad.tolist()[:10]}", flush=True)
+        print(f"nv14 2^20 {prec}: failed zones {bad.tolist()[:10]}", flush=True)
         assert bad.size <= 4
         if bad.size:
             r = oracle.burn(c["net"], c["state"][bad], 1.0, 1e-8, 1e-12)
             assert np.array_equal(r[1], status[bad]), (r[1], status[bad])
         fine = run_gpu(zb, ctx, c["net"], c["state"][idx], 1.0, 1e-10, 1e-14, precision=prec)
-        check(f"config2 2^20 {prec} sampled 256", (out[idx], status[idx], stats[idx]), ref,
+        check(f"nv14 2^20 {prec} sampled 256", (out[idx], status[idx], stats[idx]), ref,
               1e-8, 1e-12, 14, fine)
         # species sum is conserved by every reaction
         drift = np.abs(out[:, :13].sum(1) - c["state"][:, :13].sum(1)).max()
         assert drift < (1e-11 if prec == "fp64" else 1e-9), drift
 
 
-@pytest.mark.parametrize("which", ["config2", "nv14", "nv22", "nv48"])
+@pytest.mark.parametrize("which", ["nv14", "nv14", "nv22", "nv48"])
 def test_parity_tail_on_thousands_of_zones(zbm, which):
     """Thousands of zones per network, both precisions, under the self-convergence bar."""
     zb, ctx = zbm
-    if which == "config2":
-        net_d, n, Tr, Td = W.config2_network(), 3000, (1e3, 5e3), "uniform"
+    if which == "nv14":
+        net_d, n, Tr, Td = W.nv14_network(), 3000, (1e3, 5e3), "uniform"
     else:
         k = {"nv14": 0, "nv22": 1, "nv48": 2}[which]
-        ns, R, seed = W.CONFIG3_NETS[k]
+        ns, R, seed = W.BATCHED_NETS[k]
         net_d, n, Tr, Td = W.random_network(ns, R, seed), [3000, 2000, 400][k], (300.0, 6000.0), "loguniform"
     st = W.random_zones(net_d, n, seed=4242, T_range=Tr, T_dist=Td)
     ref = oracle_ref(net_d, st, 1.0, 1e-8, 1e-12)
@@ -283,7 +283,7 @@ def test_parity_tail_on_thousands_of_zones(zbm, which):
 def test_autotune_picks_the_fastest_qualifying_mapping(zbm):
     """zb_autotune times each mapping, and the chosen one then serves AUTO launches."""
     zb, ctx = zbm
-    c = W.config2(8192)
+    c = W.nv14(8192)
     net = zb.Network(ctx, c["net"])
     st = torch.tensor(c["state"], device="cuda:0")
     before = st.clone()
@@ -312,7 +312,7 @@ def test_constant_source_parity(zbm, precision):
     """A constant per-zone source on the benchmark network: GPU against the oracle with the
     same source, and the species sum moved by exactly dt * sum(a)."""
     zb, ctx = zbm
-    c = W.config2(300)
+    c = W.nv14(300)
     rng = np.random.default_rng(5)
     src = np.zeros_like(c["state"])
     src[:, :13] = rng.uniform(0.0, 1e-3, (300, 13))
@@ -327,7 +327,7 @@ def test_constant_source_parity(zbm, precision):
                                 source=torch.tensor(src, device="cuda:0"), max_steps=10000000)
         zb.sync(ctx)
         out.append((st.cpu().numpy(), status.cpu().numpy(), stats.cpu().numpy()))
-    check(f"config2 + source {precision}", out[0], (ref, fine), 1e-8, 1e-12, 14, out[1])
+    check(f"nv14 + source {precision}", out[0], (ref, fine), 1e-8, 1e-12, 14, out[1])
     drift = out[0][0][:, :13].sum(1) - c["state"][:, :13].sum(1) - src[:, :13].sum(1)
     assert np.abs(drift).max() < (1e-11 if precision == "fp64" else 1e-9)
     # the source changes the answer well beyond the tolerance
@@ -373,11 +373,11 @@ def test_loose_tolerance_parity_with_abundance_constraint(zbm, precision):
     """rtol 1e-6 on the benchmark network: zone 43 of this input is one whose unconstrained
     integration drains a species through zero; both sides reject such steps the same way."""
     zb, ctx = zbm
-    c = W.config2(96)
+    c = W.nv14(96)
     ref = oracle_ref(c["net"], c["state"], 1.0, 1e-6, 1e-10)
     net = zb.Network(ctx, c["net"])
     gpu, fine = run_pair(zb, ctx, c["net"], c["state"], 1.0, 1e-6, 1e-10, precision=precision, net=net)
-    check(f"config2 rtol 1e-6 {precision}", gpu, ref, 1e-6, 1e-10, 14, fine)
+    check(f"nv14 rtol 1e-6 {precision}", gpu, ref, 1e-6, 1e-10, 14, fine)
     assert gpu[0][:, :13].min() >= -1e-10
     net.close()
 
@@ -388,7 +388,7 @@ def test_zone_retry_parity(zbm, precision):
     steps) gives the oracle's statuses (6 for retried zones), its results within the bar at
     the tolerances each zone finished with, and counters summed over both runs."""
     zb, ctx = zbm
-    c = W.config2(160)
+    c = W.nv14(160)
     retry = (1e-6, 1e-10, 100000)
     ref = oracle.burn(c["net"], c["state"], 1.0, 1e-8, 1e-12, max_steps=1500, retry=retry)
     net = zb.Network(ctx, c["net"])
@@ -412,18 +412,18 @@ def test_zone_retry_parity(zbm, precision):
     net.close()
 
 
-@pytest.mark.parametrize("which", ["config2", "nv22", "nv48"])
+@pytest.mark.parametrize("which", ["nv14", "nv22", "nv48"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_jacobian_reuse_parity(zbm, which, precision):
     """The VODE-style reuse (jac_policy 1) against the oracle's: same statuses, results within
     the widened bar, and Jacobian/LU counts far below the step counts on both sides."""
     zb, ctx = zbm
-    if which == "config2":
-        net_d, n, Tr, Td = W.config2_network(), 400, (1e3, 5e3), "uniform"
+    if which == "nv14":
+        net_d, n, Tr, Td = W.nv14_network(), 400, (1e3, 5e3), "uniform"
     else:
         k = {"nv22": 1, "nv48": 2}[which]
-        ns, R, seed = W.CONFIG3_NETS[k]
-        net_d, n, Tr, Td = W.random_network(ns, R, seed), [0, 200, 96][k], W.CONFIG3_T_RANGE, "loguniform"
+        ns, R, seed = W.BATCHED_NETS[k]
+        net_d, n, Tr, Td = W.random_network(ns, R, seed), [0, 200, 96][k], W.BATCHED_T_RANGE, "loguniform"
     st = W.random_zones(net_d, n, seed=777, T_range=Tr, T_dist=Td)
     ref = oracle.burn(net_d, st, 1.0, 1e-8, 1e-12, jac_policy=1)
     fine = oracle.burn(net_d, st, 1.0, 1e-10, 1e-14, jac_policy=1, max_steps=10000000)
@@ -457,7 +457,7 @@ def test_rkc_parity(zbm, which):
         dt = 10.0
     else:
         k = {"nv14": 0, "nv22": 1, "nv48": 2}[which]
-        ns, R, seed = W.CONFIG3_NETS[k]
+        ns, R, seed = W.BATCHED_NETS[k]
         net_d = W.random_network(ns, R, seed)
         st = W.random_zones(net_d, [256, 128, 48][k], seed=31, T_range=(100.0, 300.0), T_dist="loguniform")
     ref = oracle.rkc(net_d, st, dt, rtol, atol)
@@ -480,7 +480,7 @@ def test_rkc_parity(zbm, which):
 
 def test_rkc_rejects_mixed_precision(zbm):
     zb, ctx = zbm
-    c = W.config2(4)
+    c = W.nv14(4)
     net = zb.Network(ctx, c["net"])
     with pytest.raises(zb.ZoneburnError) as e:
         zb.burn(ctx, net, torch.tensor(c["state"], device="cuda:0"), 1.0, 1e-6, 1e-10,
@@ -489,8 +489,8 @@ def test_rkc_rejects_mixed_precision(zbm):
     net.close()
 
 
-@pytest.mark.parametrize("which,jac_policy", [("config2", 0), ("nv22", 0), ("nv48", 0),
-                                               ("config2", 1)])
+@pytest.mark.parametrize("which,jac_policy", [("nv14", 0), ("nv22", 0), ("nv48", 0),
+                                               ("nv14", 1)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_fd_retry_parity(zbm, which, jac_policy, precision):
     """A 5-step cap fails nearly every zone, so the retry with the finite-difference Jacobian
@@ -499,14 +499,14 @@ def test_fd_retry_parity(zbm, which, jac_policy, precision):
     the integrator's own (2 at the start, one per Newton iteration, one per order-1 restart
     after three error failures)."""
     zb, ctx = zbm
-    if which == "config2":
-        net_d = W.config2_network()
+    if which == "nv14":
+        net_d = W.nv14_network()
         st = W.random_zones(net_d, 128, seed=779)
     else:
         k = {"nv22": 1, "nv48": 2}[which]
-        ns, R, seed = W.CONFIG3_NETS[k]
+        ns, R, seed = W.BATCHED_NETS[k]
         net_d = W.random_network(ns, R, seed)
-        st = W.random_zones(net_d, [0, 96, 32][k], seed=778, T_range=W.CONFIG3_T_RANGE,
+        st = W.random_zones(net_d, [0, 96, 32][k], seed=778, T_range=W.BATCHED_T_RANGE,
                             T_dist="loguniform")
     nv = net_d["n_species"] + net_d["thermal"]
     retry = (1e-8, 1e-12, 100000, "fd")
@@ -551,7 +551,7 @@ def test_fd_retry_options_are_checked(zbm):
     """The finite-difference retry Jacobian is a BDF option (no Jacobian-based solve in RKC),
     and only 'analytic' and 'fd' exist."""
     zb, ctx = zbm
-    c = W.config2(4)
+    c = W.nv14(4)
     net = zb.Network(ctx, c["net"])
     t = torch.tensor(c["state"], device="cuda:0")
     with pytest.raises(zb.ZoneburnError) as e:
@@ -568,7 +568,7 @@ def test_fd_retry_robertson_rows_per_lane(zbm, lanes):
     and four lanes per zone: a 20-step cap fails every zone, the retry at the same
     tolerances matches the oracle's (statuses 6, results within the bar)."""
     zb, ctx = zbm
-    c = W.config1(512)
+    c = W.robertson(512)
     retry = (1e-8, 1e-12, 100000, "fd")
     ref = oracle.burn(c["net"], c["state"], c["dt"], 1e-8, 1e-12, scale=c["scale"], max_steps=20,
                       retry=retry)
@@ -589,8 +589,8 @@ def test_fd_retry_robertson_rows_per_lane(zbm, lanes):
     net.close()
 
 
-@pytest.mark.parametrize("which,jac_policy", [("config2", 0), ("nv22", 0), ("nv48", 0),
-                                               ("config2", 1), ("nv48", 1)])
+@pytest.mark.parametrize("which,jac_policy", [("nv14", 0), ("nv22", 0), ("nv48", 0),
+                                               ("nv14", 1), ("nv48", 1)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_variable_coefficient_bdf_parity(zbm, which, jac_policy, precision):
     """VODE's variable-coefficient BDF form (integrator 'bdf_variable') against the oracle's
@@ -598,12 +598,12 @@ def test_variable_coefficient_bdf_parity(zbm, which, jac_policy, precision):
     bar (each side's own error from its run at rtol/100), and a step path of its own (the
     fixed form takes different steps on the same zones)."""
     zb, ctx = zbm
-    if which == "config2":
-        net_d, n, Tr, Td = W.config2_network(), 256, (1e3, 5e3), "uniform"
+    if which == "nv14":
+        net_d, n, Tr, Td = W.nv14_network(), 256, (1e3, 5e3), "uniform"
     else:
         k = {"nv22": 1, "nv48": 2}[which]
-        ns, R, seed = W.CONFIG3_NETS[k]
-        net_d, n, Tr, Td = W.random_network(ns, R, seed), [0, 128, 48][k], W.CONFIG3_T_RANGE, "loguniform"
+        ns, R, seed = W.BATCHED_NETS[k]
+        net_d, n, Tr, Td = W.random_network(ns, R, seed), [0, 128, 48][k], W.BATCHED_T_RANGE, "loguniform"
     st = W.random_zones(net_d, n, seed=781, T_range=Tr, T_dist=Td)
     nv = net_d["n_species"] + net_d["thermal"]
     ref = oracle.burn(net_d, st, 1.0, 1e-8, 1e-12, jac_policy=jac_policy, form="variable")
@@ -627,7 +627,7 @@ def test_variable_coefficient_bdf_parity(zbm, which, jac_policy, precision):
 @pytest.mark.parametrize("lanes", [1, 4])
 def test_variable_coefficient_bdf_robertson(zbm, lanes):
     zb, ctx = zbm
-    c = W.config1(512)
+    c = W.robertson(512)
     ref = oracle.burn(c["net"], c["state"], c["dt"], 1e-8, 1e-12, scale=c["scale"], form="variable")
     fine = oracle.burn(c["net"], c["state"], c["dt"], 1e-10, 1e-14, scale=c["scale"],
                        form="variable", max_steps=10000000)
@@ -650,13 +650,13 @@ def _blu_case(which):
     step), and the 14-variable network forced onto the 48-row kernel (a first panel of 14
     steps, two empty panels)."""
     if which == "nv48":
-        ns, R, seed = W.CONFIG3_NETS[2]
-        return W.random_network(ns, R, seed), 48, 0, W.CONFIG3_T_RANGE, "loguniform"
+        ns, R, seed = W.BATCHED_NETS[2]
+        return W.random_network(ns, R, seed), 48, 0, W.BATCHED_T_RANGE, "loguniform"
     if which == "nv40":
-        return W.random_network(39, 120, 612), 48, 0, W.CONFIG3_T_RANGE, "loguniform"
+        return W.random_network(39, 120, 612), 48, 0, W.BATCHED_T_RANGE, "loguniform"
     if which == "nv33":
-        return W.random_network(32, 100, 613), 48, 0, W.CONFIG3_T_RANGE, "loguniform"
-    return W.config2_network(), 64, 64, (1e3, 5e3), "uniform"
+        return W.random_network(32, 100, 613), 48, 0, W.BATCHED_T_RANGE, "loguniform"
+    return W.nv14_network(), 64, 64, (1e3, 5e3), "uniform"
 
 
 @pytest.mark.parametrize("which,integrator", [("nv48", "bdf"), ("nv48", "bdf_variable"),
@@ -690,7 +690,7 @@ def test_blocked_mfma_lu_options_are_checked(zbm):
     (EINVAL otherwise).  A network on fewer than 64 lanes per zone has no blocked form and
     takes the vector-unit LU: the same results bit for bit."""
     zb, ctx = zbm
-    ns, R, seed = W.CONFIG3_NETS[2]
+    ns, R, seed = W.BATCHED_NETS[2]
     net_d = W.random_network(ns, R, seed)
     net = zb.Network(ctx, net_d)
     t = torch.tensor(W.random_zones(net_d, 4, seed=5), device="cuda:0")
@@ -701,8 +701,8 @@ def test_blocked_mfma_lu_options_are_checked(zbm):
         assert e.value.code == zb.EINVAL, kw
     with pytest.raises(ValueError):
         zb.burn(ctx, net, t, 1.0, 1e-6, 1e-10, precision="mixed", lu="blocked")
-    small = zb.Network(ctx, W.config2_network())
-    st = W.config2(64)["state"]
+    small = zb.Network(ctx, W.nv14_network())
+    st = W.nv14(64)["state"]
     res = []
     for lu in ("mfma", "valu"):
         ts = torch.tensor(st, device="cuda:0")
@@ -722,11 +722,11 @@ def test_fp64_whole_wave_rate_factors(zbm):
     unscaled segment, bitwise equal to the two separate burns (without scales the factors
     are 1 either way)."""
     zb, ctx = zbm
-    ns, R, seed = W.CONFIG3_NETS[2]
+    ns, R, seed = W.BATCHED_NETS[2]
     net_t = W.random_network(ns, R, seed)
     net_c = W.random_network(48, 150, 614, thermal=False, log10A=(0.0, 4.0))
     rng = np.random.default_rng(615)
-    st_t = W.random_zones(net_t, 32, seed=616, T_range=W.CONFIG3_T_RANGE, T_dist="loguniform")
+    st_t = W.random_zones(net_t, 32, seed=616, T_range=W.BATCHED_T_RANGE, T_dist="loguniform")
     sc_t = np.exp(rng.normal(0.0, 0.5, (32, R)))
     st_c = W.random_zones(net_c, 32, seed=617)
     single = {}

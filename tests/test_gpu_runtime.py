@@ -18,7 +18,7 @@ def zbm():
     from paper_2608_06466_amd import zoneburn as zb
     assert torch.cuda.is_available()
     ctx = zb.Context(0)
-    nets_d = W.config3_networks()
+    nets_d = W.batched_networks()
     nets = [zb.Network(ctx, n) for n in nets_d]
     yield zb, ctx, nets_d, nets
     for n in nets:
@@ -27,11 +27,11 @@ def zbm():
 
 
 def inputs(k, nets_d, zones, seed):
-    """State (and rate scales) of config-3 network k: 0 Robertson, 1..3 random nv 14/22/48."""
+    """State (and rate scales) of network k of the batched workload: 0 Robertson, 1..3 random nv 14/22/48."""
     if k == 0:
         st, sc = W.robertson_zones(zones, seed=seed)
         return st, sc, 1.0e5
-    st = W.random_zones(nets_d[k], zones, seed=seed, T_range=W.CONFIG3_T_RANGE, T_dist="loguniform")
+    st = W.random_zones(nets_d[k], zones, seed=seed, T_range=W.BATCHED_T_RANGE, T_dist="loguniform")
     return st, None, 1.0
 
 
@@ -82,9 +82,9 @@ def test_graph_replays_match_eager(zbm):
     zb.sync(ctx)
     eager = [(s["state"].cpu().numpy(), s["status"].cpu().numpy(), s["stats"].cpu().numpy()) for s in segs]
     g = zb.Graph(ctx, segs, precision="mixed")
-    other = torch.tensor(W.config2(128)["state"], device="cuda:0")
+    other = torch.tensor(W.nv14(128)["state"], device="cuda:0")
     other0 = other.clone()
-    net2 = zb.Network(ctx, W.config2_network())
+    net2 = zb.Network(ctx, W.nv14_network())
     for rep in range(3):
         for s, i0 in zip(segs, init):
             s["state"].copy_(i0)
@@ -108,7 +108,7 @@ def test_torch_graph_capture_of_zb_burn(zbm):
     """zb.burn captured by torch.cuda.graph (the kernels clear their queues with a kernel, not a
     memset node) and replayed with the state reset eagerly in between."""
     zb, ctx, nets_d, nets = zbm
-    c = W.config2(256)
+    c = W.nv14(256)
     net = zb.Network(ctx, c["net"])
     ref = burn_alone(zb, ctx, net, c["state"], None, 1.0, 1e-8, "fp64")
     static = torch.tensor(c["state"], device="cuda:0")

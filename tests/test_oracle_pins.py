@@ -228,9 +228,9 @@ def test_order_lower_is_exact_on_polynomials(q):
 
 def _nets():
     yield "robertson", W.robertson_network(), np.array([0.7, 3e-5, 0.3, 0.0])
-    n2 = W.config2_network()
+    n2 = W.nv14_network()
     st = W.random_zones(n2, 3, seed=5)
-    yield "config2", n2, st[1]
+    yield "nv14", n2, st[1]
     n3 = W.random_network(21, 50, 302)
     yield "net22", n3, W.random_zones(n3, 2, seed=6)[0]
     yield "linear", W.linear_network(5, 3), np.array([0.1, 0.2, 0.3, 0.15, 0.25, 0.0])
@@ -255,7 +255,7 @@ def test_jacobian_equals_complex_step_derivative(name, net, y):
 
 
 def test_rhs_conserves_species_and_energy():
-    n2 = W.config2_network()
+    n2 = W.nv14_network()
     for y in W.random_zones(n2, 5, seed=9):
         f = oracle.rhs(n2, y)
         assert abs(f[:13].sum()) <= 1e-13 * np.abs(f[:13]).max()
@@ -285,7 +285,7 @@ def test_negative_abundance_is_pulled_back():
 
 
 def test_jacobian_complex_step_with_negative_abundances():
-    net = W.config2_network()
+    net = W.nv14_network()
     y = W.random_zones(net, 1, seed=12)[0]
     y[[1, 4, 7]] = [-3e-13, -1e-12, -2e-14]
     n = oracle.Net(net)
@@ -302,7 +302,7 @@ def test_jacobian_complex_step_with_negative_abundances():
 @pytest.mark.slow
 def test_zone_that_once_ran_onto_a_negative_branch():
     """Config-2 zone 602567: with plain mass action the burn ended with Y_8 = -0.044."""
-    c = W.config2()
+    c = W.nv14()
     y0 = c["state"][602567]
     net = oracle.Net(c["net"])
     sol = solve_ivp(lambda t, y: oracle.rhs(net, y), (0, 1.0), y0, method="Radau",
@@ -391,12 +391,12 @@ def test_two_body_closed_forms():
 
 
 def test_species_sum_invariant_on_benchmark_networks():
-    c2 = W.config2(64)
+    c2 = W.nv14(64)
     out, status, _ = oracle.burn(c2["net"], c2["state"], c2["dt"], RTOL, ATOL)
     assert np.all(status == 0)
     drift = np.abs(out[:, :13].sum(1) - c2["state"][:, :13].sum(1))
     assert drift.max() < 1e-12
-    c1 = W.config1(16)
+    c1 = W.robertson(16)
     out, status, _ = oracle.burn(c1["net"], c1["state"], c1["dt"], RTOL, ATOL, c1["scale"])
     assert np.all(status == 0)
     assert np.abs(out[:, :3].sum(1) - 1.0).max() < 1e-12
@@ -459,7 +459,7 @@ def test_source_alone_is_integrated_exactly():
 def test_source_moves_the_species_sum_by_its_own_sum():
     """Every reaction of the benchmark network conserves the species count, so with a source
     the sum changes by exactly dt * sum(a) (a linear invariant, kept by BDF + exact Newton)."""
-    c2 = W.config2(16)
+    c2 = W.nv14(16)
     rng = np.random.default_rng(5)
     src = np.zeros_like(c2["state"])
     src[:, :13] = rng.uniform(0.0, 1e-3, (16, 13))
@@ -481,9 +481,9 @@ def _radau_robertson():
 
 
 @functools.lru_cache(maxsize=None)
-def _radau_config2(z):
+def _radau_nv14(z):
     """scipy's Radau at rtol 1e-12 on zone z of the first 96 benchmark zones over dt = 1."""
-    c2 = W.config2(96)
+    c2 = W.nv14(96)
     return solve_ivp(lambda t, y: oracle.rhs(c2["net"], y), (0.0, 1.0), c2["state"][z, :14],
                      method="Radau", rtol=1e-12, atol=1e-20,
                      jac=lambda t, y: oracle.jac(c2["net"], y)).y[:, -1]
@@ -494,13 +494,13 @@ def test_loose_tolerance_zones_match_scipy_radau():
     derivative is small, so the local-error test alone accepts a step to -1.5e-3 (the true
     value is 8.6e-15).  The abundance constraint rejects such steps; the burn then agrees with
     an independent tight Radau solution (scipy) to the loose tolerance."""
-    c = W.config2(96)
+    c = W.nv14(96)
     idx = [43, 7]
     out, status, _ = oracle.burn(c["net"], c["state"][idx], 1.0, 1e-6, 1e-10)
     assert np.all(status == 0)
     assert out[:, :13].min() >= -1e-10
     for k, z in enumerate(idx):
-        assert gated_err(out[k, :14], _radau_config2(z), rtol=1e-6, atol=1e-10) < 1e-4, z
+        assert gated_err(out[k, :14], _radau_nv14(z), rtol=1e-6, atol=1e-10) < 1e-4, z
 
 
 # --------------------------------------- VODE-style Jacobian/LU reuse (policy 1)
@@ -526,7 +526,7 @@ def test_reuse_closed_forms_and_invariants():
     d = ya - yb
     YB = d * yb / (ya * math.exp(k * d * dt) - yb)
     assert status[0] == 0 and gated_err(out[0, :4], [YB + d, YB, 0.05 + (yb - YB), 0.1 + (yb - YB)]) < 1e-6
-    c2 = W.config2(32)
+    c2 = W.nv14(32)
     out, status, _ = oracle.burn(c2["net"], c2["state"], 1.0, RTOL, ATOL, jac_policy=1)
     assert np.all(status == 0)
     assert np.abs(out[:, :13].sum(1) - c2["state"][:, :13].sum(1)).max() < 1e-12
@@ -544,10 +544,10 @@ def test_reuse_robertson_and_benchmark_zones_match_scipy_radau():
                                      jac_policy=1)
     assert status[0] == 0 and gated_err(out[0, :3], _radau_robertson()) < 1e-6
     assert stats[0, 2] * 4 < stats[0, 0]
-    c2 = W.config2(96)
+    c2 = W.nv14(96)
     for z in (3, 43):
         out, status, stats = oracle.burn(c2["net"], c2["state"][z:z + 1], 1.0, RTOL, ATOL, jac_policy=1)
-        assert status[0] == 0 and gated_err(out[0, :14], _radau_config2(z)) < 1e-5, z
+        assert status[0] == 0 and gated_err(out[0, :14], _radau_nv14(z)) < 1e-5, z
         assert stats[0, 2] * 5 < stats[0, 0] and stats[0, 3] * 5 < stats[0, 0]
 
 
@@ -644,13 +644,13 @@ def test_vc_robertson_and_benchmark_zones_match_scipy_radau():
     out, status, stats = oracle.burn(net, np.array([[1.0, 0.0, 0.0, 0.0]]), 1e5, RTOL, ATOL,
                                      form="variable")
     assert status[0] == 0 and gated_err(out[0, :3], _radau_robertson()) < 1e-6
-    c2 = W.config2(96)
+    c2 = W.nv14(96)
     fixed = oracle.burn(c2["net"], c2["state"][:8], 1.0, RTOL, ATOL)
     var = oracle.burn(c2["net"], c2["state"][:8], 1.0, RTOL, ATOL, form="variable")
     assert np.all(var[1] == 0)
     for z in (3, 43):
         out, status, _ = oracle.burn(c2["net"], c2["state"][z:z + 1], 1.0, RTOL, ATOL, form="variable")
-        assert status[0] == 0 and gated_err(out[0, :14], _radau_config2(z)) < 1e-5, z
+        assert status[0] == 0 and gated_err(out[0, :14], _radau_nv14(z)) < 1e-5, z
     # the two forms are different methods: same answers to tolerance, different step paths
     assert not np.array_equal(var[2], fixed[2])
     with pytest.raises(ValueError):
@@ -721,7 +721,7 @@ def test_retry_reruns_failed_zones_from_their_input():
     """A step cap of 1500 fails most zones of the benchmark network; each retried zone is the
     plain burn of its original input at the retry tolerances, its status 6, its counters the
     sum of both runs, and zones that did not fail are untouched by the retry."""
-    c = W.config2(96)
+    c = W.nv14(96)
     plain = oracle.burn(c["net"], c["state"], 1.0, RTOL, ATOL, max_steps=1500)
     rt = oracle.burn(c["net"], c["state"], 1.0, RTOL, ATOL, max_steps=1500,
                      retry=(1e-6, 1e-10, 100000))
@@ -738,7 +738,7 @@ def test_retry_reruns_failed_zones_from_their_input():
 
 
 def test_retry_that_fails_again_reports_the_retry_status():
-    c = W.config2(8)
+    c = W.nv14(8)
     rt = oracle.burn(c["net"], c["state"], 1.0, RTOL, ATOL, max_steps=50, retry=(RTOL, ATOL, 60))
     assert np.all(rt[1] == 1)                   # MAXSTEPS both times
     assert np.all(rt[2][:, 0] == 110)           # 50 + 60 accepted steps
@@ -812,7 +812,7 @@ def test_fd_retry_linear_network_matches_matrix_exponential(seed):
 def test_fd_retry_on_the_benchmark_network():
     """Zones that fail a 1500-step cap, retried with finite differences at loose tolerances,
     succeed and meet those tolerances against a tight reference."""
-    c = W.config2(48)
+    c = W.nv14(48)
     rt = oracle.burn(c["net"], c["state"], 1.0, RTOL, ATOL, max_steps=1500,
                      retry=(1e-6, 1e-10, 100000, "fd"))
     plain = oracle.burn(c["net"], c["state"], 1.0, RTOL, ATOL, max_steps=1500)
@@ -860,13 +860,13 @@ def _radau_converged(net, y0, dt, n0, h0, scale=None):
 
 @pytest.mark.slow
 def test_bdf_matches_bruteforce_radau_tiny_batch():
-    c1 = W.config1(2)
+    c1 = W.robertson(2)
     out, status, _ = oracle.burn(c1["net"], c1["state"], c1["dt"], RTOL, ATOL, c1["scale"])
     for z in range(2):
         ref, conv = _radau_converged(c1["net"], c1["state"][z], c1["dt"], 20000, 1e-9, c1["scale"][z])
         assert conv < 1e-8
         assert gated_err(out[z, :3], ref) < 1e-6
-    c2 = W.config2(1)
+    c2 = W.nv14(1)
     out, status, _ = oracle.burn(c2["net"], c2["state"], c2["dt"], RTOL, ATOL)
     ref, conv = _radau_converged(c2["net"], c2["state"][0], 1.0, 20000, 1e-17)
     assert conv < 1e-7
@@ -882,8 +882,8 @@ def test_robertson_matches_scipy_radau():
 
 
 @pytest.mark.slow
-def test_config2_zones_match_scipy_radau():
-    c2 = W.config2(2)
+def test_nv14_zones_match_scipy_radau():
+    c2 = W.nv14(2)
     net = oracle.Net(c2["net"])
     out, status, _ = oracle.burn(net, c2["state"], 1.0, RTOL, ATOL)
     for z in (1,):
@@ -896,7 +896,7 @@ def test_config2_zones_match_scipy_radau():
 # ------------------------------------------------------------------- statuses
 
 def test_status_codes():
-    c2 = W.config2(4)
+    c2 = W.nv14(4)
     net = c2["net"]
     out, status, stats = oracle.burn(net, c2["state"], 1.0, RTOL, ATOL, max_steps=5)
     assert np.all(status == 1) and np.all(stats[:, 0] == 5)
@@ -914,7 +914,7 @@ def test_status_codes():
 
 
 def test_counter_consistency():
-    c2 = W.config2(16)
+    c2 = W.nv14(16)
     _, status, stats = oracle.burn(c2["net"], c2["state"], 1.0, RTOL, ATOL)
     nst, nfe, nje, nlu, nni, netf, ncf = stats.T
     assert np.array_equal(nje, nlu)
@@ -924,7 +924,7 @@ def test_counter_consistency():
 
 
 def test_step_counts_comparable_to_scipy_bdf():
-    c2 = W.config2(2)
+    c2 = W.nv14(2)
     net = oracle.Net(c2["net"])
     _, _, stats = oracle.burn(net, c2["state"], 1.0, RTOL, ATOL)
     for z in range(2):
