@@ -539,8 +539,8 @@ def main():
                     help="serving: precision of every request")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: the burn needs no communication between zones and this "
-              f"build runs on a single MI355X; --gpus {args.gpus} is not supported.", file=sys.stderr)
+        print(f"bench.py measures one GPU: zones need no communication, and one MI355X is what "
+              f"the library drives; --gpus {args.gpus} is not supported.", file=sys.stderr)
         sys.exit(2)
     {"headline": headline, "robertson": robertson, "batched": batched,
      "serving": serving}[args.workload](args)
