@@ -786,6 +786,13 @@ def test_fp64_fallback(zbm):
     assert np.array_equal(fb[0][bad], fp64[0][bad]) and np.array_equal(fb[0][~bad], mixed[0][~bad])
     assert np.array_equal(fb[2][bad], mixed[2][bad] + fp64[2][bad])
     assert np.array_equal(fb[2][~bad], mixed[2][~bad])
+    # with FP64 the option does nothing; a non-finite input ends NONFINITE, it does not fall back
+    for a_, b_ in zip(run(st, precision="fp64", fp64_fallback=True), fp64):
+        assert np.array_equal(a_, b_)
+    st_nan = st.copy()
+    st_nan[3, 2] = np.nan
+    nan = run(st_nan, precision="mixed", fp64_fallback=True)
+    assert nan[1][3] == 5 and np.array_equal(np.delete(nan[1], 3), np.delete(fb[1], 3))
     # the rescued zones against the oracle (status 7 counts as OK there)
     nv = net_d["n_species"] + net_d["thermal"]
     ref = oracle_ref(net_d, st[bad], 1.0, 1e-8, 1e-12)
