@@ -828,3 +828,17 @@ def test_fp64_fallback(zbm):
         zb.Server(ctx, 1 << 26, precision="mixed", fp64_fallback=True)
     assert e.value.code == zb.EUNSUPPORTED
     net.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("ns,R,seed", [(11, 25, 615), (19, 40, 616), (36, 110, 617)])
+def test_networks_below_the_padded_size(zbm, ns, R, seed, precision):
+    """Networks of 12, 20 and 37 variables on the 14-, 22- and 48-row kernels: the LU and the
+    solves test nv once per 8 steps, so a chunk runs a few steps past nv (identity rows of M).
+    Against the oracle, in both precisions."""
+    zb, ctx = zbm
+    net = W.random_network(ns, R, seed)
+    st = W.random_zones(net, 64, seed=seed + 1, T_range=W.BATCHED_T_RANGE, T_dist="loguniform")
+    ref = oracle_ref(net, st, 1.0, 1e-8, 1e-12)
+    gpu, fine = run_pair(zb, ctx, net, st, 1.0, 1e-8, 1e-12, precision=precision)
+    check(f"nv{ns + 1} {precision}", gpu, ref, 1e-8, 1e-12, ns + 1, fine)
