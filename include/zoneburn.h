@@ -246,7 +246,7 @@ typedef struct {
 } zb_server_opts;
 
 typedef struct {
-    int64_t zones, zones_ok;   /* zones_ok counts ZB_ZONE_OK and ZB_ZONE_OK_RETRY */
+    int64_t zones, zones_ok;   /* zones_ok counts ZB_ZONE_OK, ZB_ZONE_OK_RETRY and ZB_ZONE_OK_FP64 */
     double queue_s;          /* submit -> admission (device memory granted) */
     double first_launch_s;   /* submit -> first slice launched */
     double latency_s;        /* submit -> last slice finished on the device */
