@@ -35,7 +35,7 @@ typedef enum {
     ZB_ENOMEM = 2,     /* device or host allocation failed */
     ZB_EDEVICE = 3,    /* HIP runtime error (launch, copy, synchronize) */
     ZB_EZONES = 4,     /* zb_sync: at least one zone ended with a non-OK status */
-    ZB_EBUSY = 5,      /* server: pending queue full */
+    ZB_EBUSY = 5,      /* server: pending queue full; burn: no counter slot left for a captured call */
     ZB_ENOTFOUND = 6,  /* server: unknown ticket */
     ZB_EUNSUPPORTED = 7 /* no kernel for this (network size, mapping, precision) */
 } zb_err;
@@ -144,9 +144,11 @@ typedef struct {
                             class after the mixed-precision run, with the same options; success
                             reports ZB_ZONE_OK_FP64, a failure that run's status, and the
                             counters add up over both runs.  At most 1024 zones of each segment
-                            of a call fall back (the others keep their failure status), and at
-                            most 16 calls with the fallback may be in flight on one context.
-                            Ignored with ZB_FP64; ZB_EUNSUPPORTED in the server.  0: off. */
+                            of a call fall back (the others keep their failure status).  The
+                            lists rotate over 16 slots per context; a call whose slot an
+                            earlier call may still be using waits for that call on the host
+                            first.  Ignored with ZB_FP64; ZB_EUNSUPPORTED in the server.
+                            0: off. */
 } zb_opts;
 
 /* Create a context on HIP device `device` (allocates a small device workspace). */
@@ -168,6 +170,11 @@ zb_err zb_network_info(const zb_network *net, int32_t *n_var, int32_t *n_reactio
    stats       DEVICE [zones] counters, or NULL.
    stream      hipStream_t (as void*), NULL for the null stream.  The call is asynchronous:
                argument errors return at once, everything else surfaces in zb_sync.
+               The call takes device counters from a ring of the context (1024 slots): when
+               its slot may still be used by a call 1024 calls back, it first waits on the
+               host for that call's launches.  A call captured into a graph on `stream`
+               (stream capture) keeps counters of its own for the context's lifetime;
+               64 such calls per context, ZB_EBUSY after that (zb_graph_create has its own).
    ZB_EINVAL: zones < 0, dt not finite or <= 0, rtol <= 0, atol <= 0 (or not finite),
    NULL state with zones > 0, buffers of another device, or invalid opts.
    ZB_EUNSUPPORTED: no kernel for the network size with this mapping and precision

@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# ZB_ORACLE_LIB: another build of these sources (the mutation test loads deliberately broken
+# copies this way to show that the pins catch them)
+_LIB_PATH = os.environ.get("ZB_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 STATUS = {0: "OK", 1: "MAXSTEPS", 2: "ERRTEST", 3: "CONV", 4: "HMIN", 5: "NONFINITE"}

@@ -48,17 +48,22 @@ extern "C" zb_err zb_context_create(int device, zb_context **out)
     if (!c) return fail(ZB_ENOMEM, "host allocation failed");
     c->device = device;
     c->cus = prop.multiProcessorCount;
-    if (hipMalloc((void **)&c->ws, sizeof(unsigned long long) * (1 + QUEUE_SLOTS * MAXSEG)) != hipSuccess) {
+    const size_t nq = 1 + (size_t)(QUEUE_SLOTS + QUEUE_CAPTURE_SLOTS) * MAXSEG;
+    if (hipMalloc((void **)&c->ws, sizeof(unsigned long long) * nq) != hipSuccess) {
         delete c;
         return fail(ZB_ENOMEM, "workspace allocation failed");
     }
-    if (hipMalloc((void **)&c->fb, sizeof(unsigned long long) * FB_SLOTS * (size_t)FB_STRIDE) !=
-        hipSuccess) {
+    if (hipMalloc((void **)&c->fb, sizeof(unsigned long long) * (FB_SLOTS + FB_CAPTURE_SLOTS) *
+                                       (size_t)FB_STRIDE) != hipSuccess) {
         (void)hipFree(c->ws);
         delete c;
         return fail(ZB_ENOMEM, "workspace allocation failed");
     }
-    if (launch_reset(c->ws, 1 + QUEUE_SLOTS * MAXSEG, nullptr) != hipSuccess ||
+    c->qring.init(QUEUE_SLOTS, QUEUE_CAPTURE_SLOTS);
+    c->fbring.init(FB_SLOTS, FB_CAPTURE_SLOTS);
+    c->qev.assign(QUEUE_SLOTS, nullptr);
+    c->fbev.assign(FB_SLOTS, nullptr);
+    if (launch_reset(c->ws, nq, nullptr) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         (void)hipFree(c->ws);
         (void)hipFree(c->fb);
@@ -80,6 +85,10 @@ extern "C" zb_err zb_context_destroy(zb_context *ctx)
         for (auto s : ctx->side) (void)hipStreamDestroy(s);
         for (auto e : ctx->join) (void)hipEventDestroy(e);
         if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+        for (auto e : ctx->qev)
+            if (e) (void)hipEventDestroy(e);
+        for (auto e : ctx->fbev)
+            if (e) (void)hipEventDestroy(e);
     }
     delete ctx;
     return ZB_OK;
@@ -529,6 +538,60 @@ static zb_err side_streams(zb_context *ctx, int need)
     return ZB_OK;
 }
 
+// Launches the planned groups with the given queue counters and fallback lists.
+static zb_err launch_groups(zb_context *ctx, std::vector<Group> &groups, const RunOpts &ro,
+                            hipStream_t s0, std::vector<unsigned long long *> &queue,
+                            unsigned long long *nfail, float *ms_out,
+                            std::vector<unsigned long long *> &fb, bool serial = false)
+{
+    const int ng = (int)groups.size();
+    if (ng == 1)
+        return launch_segments(ctx, groups[0].k, groups[0].segs.data(), (int)groups[0].segs.size(),
+                               ro, s0, queue[0], nfail, ms_out, fb[0]);
+    if (serial) {
+        for (int i = 0; i < ng; ++i) {
+            zb_err e = launch_segments(ctx, groups[i].k, groups[i].segs.data(),
+                                       (int)groups[i].segs.size(), ro, s0, queue[i], nfail, nullptr,
+                                       fb[i]);
+            if (e != ZB_OK) return e;
+        }
+        return ZB_OK;
+    }
+    // Several kernel classes: the costliest runs on the caller's stream and the
+    // others on side streams forked from it and joined back, so the classes share
+    // the GPU (a class's tail is filled by the others) instead of running in turn.
+    std::lock_guard<std::mutex> lk(ctx->fork_mu);
+    const int nside = std::min(ng - 1, MAX_SIDE_STREAMS);
+    zb_err e = side_streams(ctx, nside);
+    if (e != ZB_OK) return e;
+    HIP_TRY(hipEventRecord(ctx->fork, s0));
+    for (int j = 0; j < nside; ++j) HIP_TRY(hipStreamWaitEvent(ctx->side[j], ctx->fork, 0));
+    for (int i = 0; i < ng; ++i) {
+        hipStream_t s = i == 0 ? s0 : ctx->side[(i - 1) % nside];
+        e = launch_segments(ctx, groups[i].k, groups[i].segs.data(), (int)groups[i].segs.size(),
+                            ro, s, queue[i], nfail, nullptr, fb[i]);
+        if (e != ZB_OK) return e;
+    }
+    for (int j = 0; j < nside; ++j) {
+        HIP_TRY(hipEventRecord(ctx->join[j], ctx->side[j]));
+        HIP_TRY(hipStreamWaitEvent(s0, ctx->join[j], 0));
+    }
+    return ZB_OK;
+}
+
+// Records, on s0 (which every launch of the call has joined), the event of each eager slot
+// the call used, so that the slot's next user waits for it.
+static zb_err mark_slots(zb_context *ctx, hipStream_t s0, SlotRing &ring,
+                         std::vector<hipEvent_t> &ev, const std::vector<int> &slots)
+{
+    for (int q : slots) {
+        if (!ev[q]) HIP_TRY(hipEventCreateWithFlags(&ev[q], hipEventDisableTiming));
+        HIP_TRY(hipEventRecord(ev[q], s0));
+        ring.mark(q);
+    }
+    return ZB_OK;
+}
+
 zb_err zbh::burn_impl(zb_context *ctx, const zb_segment *segs, int n, const zb_opts *opts,
                       void *stream, int force_lanes, float *ms_out, const Workspace *ws)
 {
@@ -545,46 +608,44 @@ zb_err zbh::burn_impl(zb_context *ctx, const zb_segment *segs, int n, const zb_o
     std::vector<unsigned long long *> queue(ng), fb(ng, nullptr);
     unsigned long long *nfail = ws ? ws->nfail : ctx->ws;
     const bool want_fb = ro.fallback && opts->precision == ZB_MIXED;
+    hipStream_t s0 = (hipStream_t)stream;
     if (ws) {
         for (int i = 0; i < ng; ++i) queue[i] = ws->queue + (size_t)i * MAXSEG;
         if (want_fb && !ws->fb) return fail(ZB_EUNSUPPORTED, "this caller has no FP64 fallback lists");
         if (want_fb)
             for (int i = 0; i < ng; ++i) fb[i] = ws->fb + (size_t)i * FB_STRIDE;
-    } else {
-        std::lock_guard<std::mutex> lk(ctx->mu);
-        for (int i = 0; i < ng; ++i) {
-            queue[i] = ctx->ws + 1 + (size_t)ctx->next_slot * MAXSEG;
-            ctx->next_slot = (ctx->next_slot + 1) % QUEUE_SLOTS;
-            if (want_fb) {
-                fb[i] = ctx->fb + (size_t)ctx->next_fb * FB_STRIDE;
-                ctx->next_fb = (ctx->next_fb + 1) % FB_SLOTS;
-            }
+        return launch_groups(ctx, groups, ro, s0, queue, nfail, ms_out, fb, ws->serial);
+    }
+    // The context's rotating slots.  A slot still in use by an earlier call is waited for
+    // before this call clears it; a call being captured into a graph gets slots that no
+    // other call will ever take.
+    hipStreamCaptureStatus cst = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s0, &cst));
+    const bool capturing = cst != hipStreamCaptureStatusNone;
+    std::lock_guard<std::mutex> lk(ctx->slot_mu);
+    std::vector<int> qs, fs;
+    auto wait_q = [&](int s) { (void)hipEventSynchronize(ctx->qev[s]); };
+    auto wait_f = [&](int s) { (void)hipEventSynchronize(ctx->fbev[s]); };
+    for (int i = 0; i < ng; ++i) {
+        const int q = capturing ? ctx->qring.acquire_capture() : ctx->qring.acquire(wait_q);
+        if (q < 0)
+            return fail(ZB_EBUSY, "all %d queue slots for captured calls are taken", QUEUE_CAPTURE_SLOTS);
+        queue[i] = ctx->ws + 1 + (size_t)q * MAXSEG;
+        if (!capturing) qs.push_back(q);
+        if (want_fb) {
+            const int f = capturing ? ctx->fbring.acquire_capture() : ctx->fbring.acquire(wait_f);
+            if (f < 0)
+                return fail(ZB_EBUSY, "all %d fallback lists for captured calls are taken",
+                            FB_CAPTURE_SLOTS);
+            fb[i] = ctx->fb + (size_t)f * FB_STRIDE;
+            if (!capturing) fs.push_back(f);
         }
     }
-    hipStream_t s0 = (hipStream_t)stream;
-    if (ng == 1)
-        return launch_segments(ctx, groups[0].k, groups[0].segs.data(), (int)groups[0].segs.size(),
-                               ro, s0, queue[0], nfail, ms_out, fb[0]);
-    // Several kernel classes: the costliest runs on the caller's stream and the
-    // others on side streams forked from it and joined back, so the classes share
-    // the GPU (a class's tail is filled by the others) instead of running in turn.
-    std::lock_guard<std::mutex> lk(ctx->fork_mu);
-    const int nside = std::min(ng - 1, MAX_SIDE_STREAMS);
-    e = side_streams(ctx, nside);
-    if (e != ZB_OK) return e;
-    HIP_TRY(hipEventRecord(ctx->fork, s0));
-    for (int j = 0; j < nside; ++j) HIP_TRY(hipStreamWaitEvent(ctx->side[j], ctx->fork, 0));
-    for (int i = 0; i < ng; ++i) {
-        hipStream_t s = i == 0 ? s0 : ctx->side[(i - 1) % nside];
-        e = launch_segments(ctx, groups[i].k, groups[i].segs.data(), (int)groups[i].segs.size(),
-                            ro, s, queue[i], nfail, nullptr, fb[i]);
-        if (e != ZB_OK) return e;
-    }
-    for (int j = 0; j < nside; ++j) {
-        HIP_TRY(hipEventRecord(ctx->join[j], ctx->side[j]));
-        HIP_TRY(hipStreamWaitEvent(s0, ctx->join[j], 0));
-    }
-    return ZB_OK;
+    e = launch_groups(ctx, groups, ro, s0, queue, nfail, ms_out, fb);
+    // mark the slots even after a failed launch: some of its kernels may be queued
+    zb_err em = mark_slots(ctx, s0, ctx->qring, ctx->qev, qs);
+    if (em == ZB_OK) em = mark_slots(ctx, s0, ctx->fbring, ctx->fbev, fs);
+    return e != ZB_OK ? e : em;
 }
 
 extern "C" zb_err zb_burn(zb_context *ctx, const zb_network *net, double *state, int64_t zones,

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "zb_internal.h"
+#include "zb_slots.h"
 #include "zoneburn.h"
 
 namespace zbh {
@@ -22,7 +23,10 @@ zb_err fail(zb_err e, const char *fmt, ...);
             return ::zbh::fail(ZB_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
+// Zone-queue counter slots of a context (MAXSEG counters each): a ring for eager calls, and
+// slots that a call captured into a graph keeps for good (SlotRing).
 constexpr int QUEUE_SLOTS = 1024;
+constexpr int QUEUE_CAPTURE_SLOTS = 64;
 
 struct DeviceGuard {
     int prev = -1;
@@ -47,11 +51,15 @@ struct Workspace {
     int launches;
     unsigned long long *nfail;
     unsigned long long *fb;      // launches x FB_STRIDE FP64 fallback lists (nullptr: none)
+    bool serial = false;         // every launch on the caller's stream, one after another
 };
 
-// FP64 fallback lists of a context: calls with the fallback take them in turn, so at most
-// this many such calls may be in flight on one context at a time.
+
+// FP64 fallback lists of a context: calls with the fallback take them in turn, and a call
+// whose list is still in use by an earlier one first waits for it; captured calls take
+// lists of their own.
 constexpr int FB_SLOTS = 16;
+constexpr int FB_CAPTURE_SLOTS = 4;
 
 const zb::KernelInfo *find_kernel(int nv, int lanes, int mixed, int jac);
 const zb::KernelInfo *kernel_for(int nv, int lanes, int mixed, int method);
@@ -84,10 +92,14 @@ int blocks_per_cu(const zb::KernelInfo *k, int max_nr);
 struct zb_context {
     int device = 0;
     int cus = 0;
-    unsigned long long *ws = nullptr;   // [0] failed zones, then QUEUE_SLOTS x MAXSEG queue counters
-    int next_slot = 0;
-    unsigned long long *fb = nullptr;   // FB_SLOTS x FB_STRIDE FP64 fallback lists
-    int next_fb = 0;
+    // [0] failed zones, then (QUEUE_SLOTS + QUEUE_CAPTURE_SLOTS) x MAXSEG queue counters
+    unsigned long long *ws = nullptr;
+    // (FB_SLOTS + FB_CAPTURE_SLOTS) x FB_STRIDE FP64 fallback lists
+    unsigned long long *fb = nullptr;
+    // slot rotation: each eager slot's event is recorded after the last launch that uses it
+    std::mutex slot_mu;
+    zbh::SlotRing qring, fbring;
+    std::vector<hipEvent_t> qev, fbev;
     std::mutex mu;
     // autotuned lanes per zone, keyed by (nv, nr, precision)
     struct Tuned { int nv, nr, prec, lanes; };

@@ -210,11 +210,35 @@ def _opts(precision, lanes, max_steps, retry=None, jac_policy=0, integrator=0, l
                  int(retry[2]), jp, it, rj, lv, int(bool(fp64_fallback)))
 
 
-def _check_state(net, state):
+def _check_state(net, state, cuda=True):
     import torch
-    if not (isinstance(state, torch.Tensor) and state.is_cuda and state.dtype == torch.float64
-            and state.dim() == 2 and state.shape[1] == net.ns + 1 and state.is_contiguous()):
+    if not (isinstance(state, torch.Tensor) and (state.is_cuda or not cuda)
+            and state.dtype == torch.float64 and state.dim() == 2
+            and state.shape[1] == net.ns + 1 and state.is_contiguous()):
         raise ValueError("state must be a contiguous float64 CUDA tensor [zones][ns+1]")
+
+
+def _check_buf(name, t, dtype, shape, device):
+    """A per-zone buffer handed to the library: dtype, shape, contiguity and the state's device
+    (the kernels index it by zone; anything else would read or write out of bounds)."""
+    import torch
+    if t is None:
+        return
+    if not (isinstance(t, torch.Tensor) and t.dtype == dtype and tuple(t.shape) == tuple(shape)
+            and t.is_contiguous() and t.device == device):
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor {list(shape)} on {device}")
+
+
+def _check_segment(s, cuda=True):
+    """Validates one segment dict (state, rate_scale, status, stats, source)."""
+    import torch
+    net, st = s["net"], s["state"]
+    _check_state(net, st, cuda)
+    z = st.shape[0]
+    _check_buf("rate_scale", s.get("rate_scale"), torch.float64, (z, net.nr), st.device)
+    _check_buf("status", s.get("status"), torch.int32, (z,), st.device)
+    _check_buf("stats", s.get("stats"), torch.int32, (z, 7), st.device)
+    _check_buf("source", s.get("source"), torch.float64, tuple(st.shape), st.device)
 
 
 def burn(ctx, net, state, dt, rtol, atol, rate_scale=None, precision="fp64", lanes=0,
@@ -237,10 +261,7 @@ def burn(ctx, net, state, dt, rtol, atol, rate_scale=None, precision="fp64", lan
                    fp64_fallback=fp64_fallback)
         return status, stats
     zones = state.shape[0]
-    if rate_scale is not None and (rate_scale.dtype != torch.float64 or not rate_scale.is_cuda
-                                   or tuple(rate_scale.shape) != (zones, net.nr)
-                                   or not rate_scale.is_contiguous()):
-        raise ValueError("rate_scale must be a contiguous float64 CUDA tensor [zones][R]")
+    _check_buf("rate_scale", rate_scale, torch.float64, (zones, net.nr), state.device)
     status = torch.empty(zones, dtype=torch.int32, device=state.device) if want_status else None
     stats = torch.empty((zones, 7), dtype=torch.int32, device=state.device) if want_stats else None
     o = _opts(precision, lanes, max_steps, retry, jac_policy, integrator, lu, fp64_fallback)
@@ -251,19 +272,13 @@ def burn(ctx, net, state, dt, rtol, atol, rate_scale=None, precision="fp64", lan
 
 
 def _src_ptr(src, state):
-    if src is None:
-        return None
-    import torch
-    if not (isinstance(src, torch.Tensor) and src.is_cuda and src.dtype == torch.float64
-            and src.shape == state.shape and src.is_contiguous()):
-        raise ValueError("source must be a contiguous float64 CUDA tensor shaped like state")
-    return src.data_ptr()
+    return None if src is None else src.data_ptr()
 
 
 def _segments(segments):
     arr = (_Segment * len(segments))()
     for i, s in enumerate(segments):
-        _check_state(s["net"], s["state"])
+        _check_segment(s)
         arr[i] = _Segment(s["net"].h.value, s["state"].data_ptr(), s["state"].shape[0],
                           float(s["dt"]), float(s["rtol"]), float(s["atol"]),
                           _ptr(s.get("rate_scale")).value if s.get("rate_scale") is not None else None,

@@ -80,3 +80,35 @@ def test_struct_layouts_match_the_binding(tmp_path):
         assert int(got[cname]) == ctypes.sizeof(py), cname
         for f, _ in py._fields_:
             assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, (cname, f)
+
+
+def test_segment_buffers_are_validated():
+    """Every per-zone buffer of a segment is checked for dtype, shape, contiguity and device
+    before its pointer reaches the library (host tensors stand in for device ones here)."""
+    torch = pytest.importorskip("torch")
+    from types import SimpleNamespace
+    from paper_2608_06466_amd import zoneburn as zb
+    net = SimpleNamespace(ns=3, nr=5)
+    z = 7
+    good = dict(net=net, state=torch.zeros(z, 4, dtype=torch.float64),
+                rate_scale=torch.ones(z, 5, dtype=torch.float64),
+                status=torch.zeros(z, dtype=torch.int32), stats=torch.zeros(z, 7, dtype=torch.int32),
+                source=torch.zeros(z, 4, dtype=torch.float64))
+    zb._check_segment(good, cuda=False)
+    bad = [("rate_scale", torch.ones(z - 1, 5, dtype=torch.float64)),
+           ("rate_scale", torch.ones(z, 5, dtype=torch.float32)),
+           ("rate_scale", torch.ones(5, z, dtype=torch.float64).t()),
+           ("status", torch.zeros(z - 1, dtype=torch.int32)),
+           ("status", torch.zeros(z, dtype=torch.int64)),
+           ("stats", torch.zeros(z, 6, dtype=torch.int32)),
+           ("stats", torch.zeros(7, z, dtype=torch.int32).t()),
+           ("source", torch.zeros(z, 3, dtype=torch.float64)),
+           ("state", torch.zeros(z, 4, dtype=torch.float32))]
+    for key, val in bad:
+        s = dict(good)
+        s[key] = val
+        with pytest.raises(ValueError):
+            zb._check_segment(s, cuda=False)
+    # a host state is refused where the library needs device memory
+    with pytest.raises(ValueError):
+        zb._check_segment(good)

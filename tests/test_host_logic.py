@@ -1,0 +1,28 @@
+"""Host-side logic of the runtime built for the CPU alone, under AddressSanitizer and
+UndefinedBehaviorSanitizer (no GPU, no HIP): the context's slot rotation."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2608_06466_amd", "csrc")
+HERE = os.path.join(ROOT, "tests", "host")
+
+
+def _build_and_run(src, tmp_path):
+    if not shutil.which("g++"):
+        pytest.skip("g++ not found")
+    exe = str(tmp_path / "prog")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=all", "-I", CSRC, os.path.join(HERE, src), "-o", exe],
+                   check=True)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    return r.stdout
+
+
+def test_slot_rotation_waits_for_the_previous_user(tmp_path):
+    out = _build_and_run("slots_test.cpp", tmp_path)
+    assert "slots ok" in out

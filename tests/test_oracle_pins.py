@@ -931,3 +931,59 @@ def test_step_counts_comparable_to_scipy_bdf():
         sol = solve_ivp(lambda t, y: oracle.rhs(net, y), (0, 1.0), c2["state"][z], method="BDF",
                         rtol=RTOL, atol=ATOL, jac=lambda t, y: oracle.jac(net, y))
         assert 0.33 < stats[z, 0] / (sol.t.size - 1) < 3.0
+
+
+# ---------------------------------------------------------------- Robertson, as printed
+
+def _robertson_textbook(t, y, k1=0.04, k2=3.0e7, k3=1.0e4):
+    """Robertson's kinetics written out from the standard statement of the problem, not
+    from the network descriptor: y1' = -k1 y1 + k3 y2 y3, y2' = k1 y1 - k3 y2 y3 - k2 y2^2,
+    y3' = k2 y2^2."""
+    y1, y2, y3 = y
+    return np.array([-k1 * y1 + k3 * y2 * y3, k1 * y1 - k3 * y2 * y3 - k2 * y2 * y2, k2 * y2 * y2])
+
+
+def _robertson_textbook_jac(t, y, k1=0.04, k2=3.0e7, k3=1.0e4):
+    y1, y2, y3 = y
+    return np.array([[-k1, k3 * y3, k3 * y2],
+                     [k1, -k3 * y3 - 2 * k2 * y2, -k3 * y2],
+                     [0.0, 2 * k2 * y2, 0.0]])
+
+
+def test_robertson_network_is_the_textbook_ode():
+    """The oracle's Robertson right-hand side and Jacobian equal the textbook formulas, at
+    random non-negative states and with per-rate scale factors."""
+    net = W.robertson_network()
+    rng = np.random.default_rng(17)
+    for _ in range(50):
+        y = rng.uniform(0.0, 1.0, 3) * np.array([1.0, 1e-4, 1.0])
+        s = np.exp(0.1 * rng.normal(size=3))
+        k = (0.04 * s[0], 3.0e7 * s[1], 1.0e4 * s[2])
+        # rounding only: the terms may be summed in another order, and the descriptor holds
+        # ln k, so exp(ln k) carries a relative error up to |ln k| eps (about 4e-15 for 3e7)
+        scale = k[0] * y[0] + k[2] * y[1] * y[2] + k[1] * y[1] ** 2
+        f = oracle.rhs(net, y, s)
+        ft = _robertson_textbook(0.0, y, *k)
+        assert np.max(np.abs(f - ft)) <= 1e-14 * scale, (f, ft)
+        J = oracle.jac(net, y, s)
+        Jt = _robertson_textbook_jac(0.0, y, *k)
+        jscale = k[0] + k[2] * (y[1] + y[2]) + 2 * k[1] * y[1]
+        assert np.max(np.abs(J - Jt)) <= 1e-14 * jscale, (J, Jt)
+
+
+@pytest.mark.slow
+def test_robertson_burn_matches_the_textbook_solution():
+    """A burn over [0, 1e5] from (1, 0, 0) against scipy's Radau on the textbook ODE at
+    rtol 1e-12, and against the commonly quoted y(1e5) ~ (1.786592e-2, 7.274752e-8,
+    9.821340e-1)."""
+    ref = solve_ivp(_robertson_textbook, (0.0, 1e5), [1.0, 0.0, 0.0], method="Radau",
+                    rtol=1e-12, atol=1e-20, jac=_robertson_textbook_jac).y[:, -1]
+    assert np.allclose(ref, [1.786592e-2, 7.274752e-8, 9.821340e-1], rtol=2e-6)
+    net = W.robertson_network()
+    out, status, _ = oracle.burn(net, np.array([[1.0, 0.0, 0.0, 0.0]]), 1e5, RTOL, ATOL)
+    assert status[0] == 0
+    assert gated_err(out[0, :3], ref) < 1e-6
+    fine, status, _ = oracle.burn(net, np.array([[1.0, 0.0, 0.0, 0.0]]), 1e5, 1e-11, 1e-16,
+                                  max_steps=10000000)
+    assert status[0] == 0
+    assert gated_err(fine[0, :3], ref, 1e-11, 1e-16) < 1e-6
