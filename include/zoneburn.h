@@ -212,6 +212,21 @@ typedef struct {
 zb_err zb_burn_batch(zb_context *ctx, const zb_segment *segs, int32_t n_seg, const zb_opts *opts,
                      void *stream);
 
+/* zb_burn_batch for callers that cannot allocate device memory or other runtime resources
+   while they burn (code under stream capture, tight serving loops, harnesses that forbid
+   allocation): the call allocates nothing, creates no stream or event and never waits on the
+   host.  Its zone-queue counters live in a static device array of the library (4 launches x
+   8 counters, 256 bytes per GPU, held until the process ends) instead of the context's ring;
+   the context (created beforehand) supplies the device and the failed-zone count of zb_sync.
+   Every kernel class of the call runs on `stream`, one after another (no side streams).
+   Results are bitwise those of zb_burn_batch with the same arguments.
+   ZB_EINVAL as zb_burn_batch, and when the segments need more than 4 launches (kernel
+   classes, 8 segments per launch).  ZB_EUNSUPPORTED with fp64_fallback in ZB_MIXED (its
+   lists are not in the static array).  All such calls on one GPU share the array: calls that
+   overlap in time on one GPU (other streams, other threads, other contexts) race; order them. */
+zb_err zb_burn_batch_noalloc(zb_context *ctx, const zb_segment *segs, int32_t n_seg,
+                             const zb_opts *opts, void *stream);
+
 /* Fixed-shape repeats as a HIP graph: the burn of these segments (buffers, sizes, tolerances
    and options fixed at creation) is captured once and replayed by zb_graph_launch, each
    replay burning whatever the buffers then hold.  The graph owns its work-queue counters

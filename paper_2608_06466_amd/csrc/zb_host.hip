@@ -31,6 +31,32 @@ zb_err zbh::fail(zb_err e, const char *fmt, ...)
 
 // ------------------------------------------------------------------ context
 
+// Scratch of zb_burn_batch_noalloc: the zone-queue counters of its launches.  Each GPU the
+// library runs on holds its own copy until the process ends; every such call on a GPU
+// shares that copy (calls that overlap on one GPU race).  In host code the name is not a
+// device address: the address is taken once per device with hipGetSymbolAddress (at
+// context creation) and only that address is used.
+static __device__ __align__(256) unsigned long long scratch[STATIC_LAUNCHES * MAXSEG];
+
+static std::mutex g_scratch_mu;
+static unsigned long long *g_scratch_ptr[64];
+
+// This device's address of `scratch` (the device is current).
+static zb_err static_scratch_address(int device, unsigned long long **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device < 0 || device >= 64) return fail(ZB_EUNSUPPORTED, "device %d: no scratch slot", device);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(ZB_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_ptr[device] = (unsigned long long *)ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return ZB_OK;
+}
+
 extern "C" zb_err zb_context_create(int device, zb_context **out)
 {
     if (!out) return fail(ZB_EINVAL, "out is NULL");
@@ -58,6 +84,12 @@ extern "C" zb_err zb_context_create(int device, zb_context **out)
         (void)hipFree(c->ws);
         delete c;
         return fail(ZB_ENOMEM, "workspace allocation failed");
+    }
+    if (static_scratch_address(device, &c->static_scratch) != ZB_OK) {
+        (void)hipFree(c->ws);
+        (void)hipFree(c->fb);
+        delete c;
+        return ZB_EDEVICE;
     }
     c->qring.init(QUEUE_SLOTS, QUEUE_CAPTURE_SLOTS);
     c->fbring.init(FB_SLOTS, FB_CAPTURE_SLOTS);
@@ -670,6 +702,25 @@ extern "C" zb_err zb_burn_batch(zb_context *ctx, const zb_segment *segs, int32_t
                                 const zb_opts *opts, void *stream)
 {
     return burn_impl(ctx, segs, n_seg, opts, stream);
+}
+
+extern "C" zb_err zb_burn_batch_noalloc(zb_context *ctx, const zb_segment *segs, int32_t n_seg,
+                                        const zb_opts *opts, void *stream)
+{
+    if (!ctx) return fail(ZB_EINVAL, "NULL context");
+    if (!ctx->static_scratch) return fail(ZB_EDEVICE, "no static scratch on this context's device");
+    if (opts && opts->fp64_fallback && opts->precision == ZB_MIXED)
+        return fail(ZB_EUNSUPPORTED, "fp64_fallback needs lists the static scratch does not hold");
+    int launches = 0;
+    zb_err e = (zb_err)count_launches(ctx, segs, n_seg, opts, &launches);   // validates everything
+    if (e != ZB_OK) return e;
+    if (launches > STATIC_LAUNCHES)
+        return fail(ZB_EINVAL, "the call needs %d launches (kernel classes, at most %d segments "
+                               "each); the static scratch holds the counters of %d",
+                    launches, MAXSEG, STATIC_LAUNCHES);
+    Workspace ws{ctx->static_scratch, STATIC_LAUNCHES, ctx->ws, nullptr};
+    ws.serial = true;
+    return burn_impl(ctx, segs, n_seg, opts, stream, 0, nullptr, &ws);
 }
 
 extern "C" zb_err zb_sync(zb_context *ctx, void *stream, int64_t *n_failed)

@@ -54,6 +54,9 @@ struct Workspace {
     bool serial = false;         // every launch on the caller's stream, one after another
 };
 
+// Kernel classes (launches) one call of the allocation-free entry point may make: the
+// zone-queue counters of that many launches sit in the library's static device array.
+constexpr int STATIC_LAUNCHES = 4;
 
 // FP64 fallback lists of a context: calls with the fallback take them in turn, and a call
 // whose list is still in use by an earlier one first waits for it; captured calls take
@@ -100,6 +103,8 @@ struct zb_context {
     std::mutex slot_mu;
     zbh::SlotRing qring, fbring;
     std::vector<hipEvent_t> qev, fbev;
+    // this device's copy of the static scratch array (zb_burn_batch_noalloc)
+    unsigned long long *static_scratch = nullptr;
     std::mutex mu;
     // autotuned lanes per zone, keyed by (nv, nr, precision)
     struct Tuned { int nv, nr, prec, lanes; };

@@ -88,6 +88,7 @@ def lib():
             "zb_burn": [p, p, p, i64, d, d, d, p, C.POINTER(_Opts), p, p, p],
             "zb_sync": [p, p, C.POINTER(i64)],
             "zb_burn_batch": [p, C.POINTER(_Segment), i32, C.POINTER(_Opts), p],
+            "zb_burn_batch_noalloc": [p, C.POINTER(_Segment), i32, C.POINTER(_Opts), p],
             "zb_get_mapping": [p, p, i32, C.POINTER(i32)],
             "zb_autotune": [p, p, p, i64, d, d, d, i32, C.POINTER(i32), C.POINTER(C.c_float)],
             "zb_graph_create": [p, C.POINTER(_Segment), i32, C.POINTER(_Opts), C.POINTER(p)],
@@ -296,6 +297,17 @@ def burn_batch(ctx, segments, precision="fp64", lanes=0, max_steps=0, stream=Non
     o = _opts(precision, lanes, max_steps, retry, jac_policy, integrator, lu, fp64_fallback)
     _check(lib().zb_burn_batch(ctx.h, arr, len(segments), C.byref(o), _stream_handle(stream)),
            "zb_burn_batch")
+
+
+def burn_batch_noalloc(ctx, segments, precision="fp64", lanes=0, max_steps=0, stream=None,
+                       retry=None, jac_policy=0, integrator="bdf", lu="valu", fp64_fallback=False):
+    """burn_batch through zb_burn_batch_noalloc: no device allocation, no stream or event
+    creation, counters in the library's static device array (at most 4 kernel classes; every
+    class on `stream` in turn)."""
+    arr = _segments(segments)
+    o = _opts(precision, lanes, max_steps, retry, jac_policy, integrator, lu, fp64_fallback)
+    _check(lib().zb_burn_batch_noalloc(ctx.h, arr, len(segments), C.byref(o),
+                                       _stream_handle(stream)), "zb_burn_batch_noalloc")
 
 
 class Graph:
