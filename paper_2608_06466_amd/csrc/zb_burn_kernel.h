@@ -82,10 +82,13 @@ __device__ __forceinline__ double4 gload(const double4 *p)
     return make_double4(a.x, a.y, b.x, b.y);
 }
 
+// Every DPP pattern used here (quad_perm, row_half_mirror, row_mirror, row_newbcast) reads a
+// lane of the same 16-lane row, so no lane keeps its old value: the move takes no old operand
+// (no extra instruction to set one).
 template <int CTRL>
 __device__ __forceinline__ int dpp_i(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
 }
 
 template <int CTRL>
@@ -148,8 +151,20 @@ __device__ __forceinline__ void sfor(F &&f)
 }
 
 struct OpAdd { template <class T> __device__ T operator()(T a, T b) const { return a + b; } };
-struct OpMax { template <class T> __device__ T operator()(T a, T b) const { return a > b ? a : b; } };
-struct OpMin { template <class T> __device__ T operator()(T a, T b) const { return a < b ? a : b; } };
+// max and min of floating values as single v_max / v_min instructions (the same result as a
+// compare and select for every non-NaN value)
+struct OpMax {
+    template <class T> __device__ T operator()(T a, T b) const
+    {
+        if constexpr (std::is_floating_point_v<T>) return fmax(a, b); else return a > b ? a : b;
+    }
+};
+struct OpMin {
+    template <class T> __device__ T operator()(T a, T b) const
+    {
+        if constexpr (std::is_floating_point_v<T>) return fmin(a, b); else return a < b ? a : b;
+    }
+};
 
 // Exchange across 16-lane rows without LDS (gfx950 v_permlane16_swap /
 // v_permlane32_swap).  Swapping a register with itself leaves, in the pair
@@ -448,16 +463,13 @@ struct Ctx {
 template <int NVP, int L>
 __device__ __forceinline__ int row_of(const Ctx &c, int s) { return c.gl + L * s; }
 
-// Per-reaction rate factors in LDS: always, except in the trimmed layout of a launch without
-// rate scales (all factors 1).
+// Per-reaction rate factors in LDS, used when the launch has any (rate scales, or the constant
+// rates of a network without temperature); otherwise they are all 1 and neither written nor
+// read (the trimmed layout has no room for them then).
 template <int NVP, int L, class LT>
 __device__ __forceinline__ bool rates_in_lds(const Ctx &c)
 {
-    constexpr int RPL = (NVP + L - 1) / L;
-    if constexpr (lds_trim(L, RPL, jac_f32(NVP, sizeof(LT) == 4)))
-        return c.rates;
-    else
-        return true;
+    return c.rates;
 }
 
 // Element type of the Jacobian rows in LDS.
@@ -498,6 +510,22 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
     using JT = JacT<NVP, LT>;
     JT *jb = (JT *)(c.S + c.lay.jbuf);
 
+    // The 14-row kernels with a Jacobian every step (one row a lane, registers to spare): a
+    // row's whole list, up to 6 entry pairs, is loaded first, so its latency overlaps the
+    // rate evaluation, and walked from registers.  Elsewhere the extra registers cost
+    // occupancy or spills, and the list is streamed.
+    constexpr int PMAX = (RPL == 1 && NVP == 14 && L == 16) ? 6 : 0;
+    int4 pre[PMAX > 0 ? PMAX : 1];
+    const int n2 = N.inv_len / 2;
+    const bool use_pre = PMAX > 0 && c.jac_policy == 0 && n2 <= PMAX;
+    if constexpr (PMAX > 0) {
+        const int i0 = row_of<NVP, L>(c, 0);
+        const int4 *l0 = (const int4 *)(N.inv + (i0 < N.ns ? i0 : 0) * N.inv_len);
+        sfor<0, PMAX>([&](auto P) {
+            pre[P] = make_int4(-1, 0, -1, 0);
+            if (use_pre && P < n2) pre[P] = gload(l0 + P);
+        });
+    }
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
         int i = row_of<NVP, L>(c, s);
@@ -605,14 +633,20 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
                     }
                 }
             };
-            const int n2 = N.inv_len / 2;
-            int4 nen = n2 > 0 ? gload(lst) : make_int4(-1, 0, -1, 0);
-            for (int e = 0; e < n2; ++e) {
-                const int4 en = nen;
-                if (e + 1 < n2) nen = gload(lst + e + 1);
-                if (en.x < 0) break;
-                pair(en);
-                if (en.z < 0) break;
+            if (use_pre) {
+                // entries past the row's list are padding (x < 0), skipped
+                sfor<0, (PMAX > 0 ? PMAX : 1)>([&](auto P) {
+                    if (P < n2 && pre[P].x >= 0) pair(pre[P]);
+                });
+            } else {
+                int4 nen = n2 > 0 ? gload(lst) : make_int4(-1, 0, -1, 0);
+                for (int e = 0; e < n2; ++e) {
+                    const int4 en = nen;
+                    if (e + 1 < n2) nen = gload(lst + e + 1);
+                    if (en.x < 0) break;
+                    pair(en);
+                    if (en.z < 0) break;
+                }
             }
             if (WANTJ && N.thermal) {
                 jrow[N.ns] = (JT)jit;
@@ -1007,6 +1041,25 @@ __device__ __forceinline__ void lu_factor(const Ctx &c, Zone<NVP, L, LT> &z)
         }
         int pl = p & (L - 1);
         int ps = p / L;
+        if constexpr (RPL == 1 && L >= 2) {
+            // one row per lane: the pivot row is read from the pivot lane's registers through
+            // the LDS crossbar (ds_bpermute), with no store and reload
+            const int src = (int)(threadIdx.x & (64 - L)) + pl;
+            LT pr[NVP];
+            sfor<k, NVP>([&](auto J) { pr[J] = gather(z.M[0][J], src); });
+            const LT rinv = recip(pr[k]);
+            const int i = c.gl;
+            if (i == p) {
+                z.pstep[0] = k;
+                z.dinv[0] = rinv;
+            }
+            const bool act = z.pstep[0] > k;
+            const LT l = act ? z.M[0][k] * rinv : LT(0);
+            if (act) z.M[0][k] = l;
+            sfor<k + 1, NVP>([&](auto J) { z.M[0][J] = fma(-l, pr[J], z.M[0][J]); });
+            if (c.gl == k) z.pivlane = p;
+            return;
+        }
         if (c.gl == pl) {
             sfor<k, NVP>([&](auto J) {
                 if constexpr (RPL == 1) {
@@ -1316,7 +1369,9 @@ __device__ __forceinline__ bool newton(const Ctx &c, Zone<NVP, L, LT> &z, double
         } else {
             double rho = d / dprev;
             if (rho < 1.0 && rho * d / (1.0 - rho) <= tau) return true;
-            if (rho >= 1.0 || pow(rho, (double)(4 - m)) * d / (1.0 - rho) > tau) return false;
+            // rho^(4-m) as products (m = 1, 2, 3): the same value as the power up to rounding
+            const double rp = (m == 1) ? rho * rho * rho : ((m == 2) ? rho * rho : rho);
+            if (rho >= 1.0 || rp * d / (1.0 - rho) > tau) return false;
         }
         dprev = d;
     }
@@ -1867,6 +1922,8 @@ constexpr int min_waves_per_eu()
     // the reuse kernels keep the factors live across steps: bounded to two waves too
     // the 8-row kernel fits three waves with a Jacobian every step
     if (NVP == 8 && L == 8 && (JP == METHOD_BDF || JP == METHOD_BDF_VC)) return 3;
+    // RKC keeps no matrix: four waves fit (the compiler would take two registers more)
+    if (JP == METHOD_RKC) return 4;
     return ((NVP >= 48 && L == 64) || (method_jac(JP) == 1 && L >= 16)) ? 2 : 1;
 }
 
