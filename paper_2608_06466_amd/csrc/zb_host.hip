@@ -250,9 +250,12 @@ static size_t launch_lds(const KernelInfo *k, int max_nr, bool rates = true)
     return (size_t)G * lay.total * sizeof(double);
 }
 
+// Lanes per zone when the caller does not choose.  Up to 4 variables, 4 lanes (one row each)
+// beat one lane with every row: Robertson 2^19 zones in 64 against 79 ms, 4096 zones in 4.4
+// against 9.3 ms (MI355X, mixed precision).
 static int default_lanes(int nv)
 {
-    if (nv <= 4) return 1;
+    if (nv <= 4) return 4;
     if (nv <= 8) return 8;
     if (nv <= 16) return 16;
     if (nv <= 32) return 32;
