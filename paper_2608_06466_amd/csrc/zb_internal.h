@@ -130,10 +130,11 @@ __host__ __device__ inline LdsLayout lds_layout(int nvp, int L, int rpl, int nr,
     o.jbuf = p;                       // Jacobian rows with an odd stride (no bank conflicts)
     p += jf32 ? (nvp * (nvp + 1) + 1) / 2 : nvp * (nvp + 1);
     o.vc = p;   p += vc ? VC_SLOTS : 0;
-    // One or a few lanes a zone: consecutive zones' areas start an odd number of doubles
-    // apart, so a wave's same-slot accesses spread over all LDS banks (a stride of a multiple
-    // of 8 dwords put the 64 zones of a wave on 8 banks).  Wider groups keep an even stride.
-    o.total = L <= 4 ? (p | 1) : ((p + 1) & ~1);
+    // One or two lanes a zone: consecutive zones' areas start an odd number of doubles apart,
+    // so a wave's same-slot accesses spread over all LDS banks (a stride of a multiple of 8
+    // dwords put the 64 zones of a wave on 8 banks).  Wider groups keep an even stride (odd
+    // raised the 4-lane kernels' bank conflicts from 0.02 to 0.6 per LDS-active cycle).
+    o.total = L < 4 ? (p | 1) : ((p + 1) & ~1);
     return o;
 }
 
