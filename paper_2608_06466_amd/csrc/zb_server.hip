@@ -25,6 +25,7 @@
 #include <thread>
 
 #include "zb_host_internal.h"
+#include "zb_sched.h"
 
 using namespace zb;
 using namespace zbh;
@@ -37,86 +38,35 @@ double now_s()
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-constexpr size_t ALIGN = 256;
-
-// First-fit allocator over one device block; offsets only, no device access.
-class Arena {
-public:
-    void init(size_t bytes)
-    {
-        free_.clear();
-        free_[0] = bytes;
-        size_ = bytes;
-        used_ = 0;
-    }
-    bool alloc(size_t bytes, size_t *off)
-    {
-        bytes = (bytes + ALIGN - 1) & ~(ALIGN - 1);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                size_t rest = it->second - bytes, at = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[at] = rest;
-                used_ += bytes;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes)
-    {
-        bytes = (bytes + ALIGN - 1) & ~(ALIGN - 1);
-        used_ -= bytes;
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    size_t used() const { return used_; }
-    size_t size() const { return size_; }
-
-private:
-    std::map<size_t, size_t> free_;
-    size_t size_ = 0, used_ = 0;
-};
-
-enum ReqState { PENDING, ADMITTED, DONE };
-
-struct Request {
-    uint64_t ticket = 0;
+struct Request : SchedRequest {
     const zb_network *net = nullptr;
     const KernelInfo *k = nullptr;
     int row = 0;
-    int64_t zones = 0;
     double dt = 0, rtol = 0, atol = 0;
     std::vector<double> in_state, in_scale;
-    size_t off = 0, bytes = 0;
     double *state = nullptr, *scale = nullptr;
     int32_t *status = nullptr;
     zb_zone_stats *stats = nullptr;
     hipEvent_t uploaded = nullptr;
-    double cost = 1.0;       // relative device work per zone (see zb_server_submit)
-    int64_t next = 0;        // first zone not yet in a launch
-    int64_t finished = 0;    // zones whose launch has completed
-    ReqState st = PENDING;
-    double t_submit = 0, t_admit = 0, t_first = 0, t_done = 0;
 };
 
-struct Launch {
-    hipEvent_t done = nullptr;
-    int stream = 0;
-    int qblock = 0;
-    std::vector<std::pair<Request *, int64_t>> parts;
+// The scheduler's device side: copies on the copy stream, launches on the server's
+// streams, one event and one block of zone-queue counters per launch in flight.
+struct HipDev {
+    struct Handle {
+        hipEvent_t done = nullptr;
+        int qblock = 0;
+    };
+    zb_server *S = nullptr;
+    zb_err err = ZB_EDEVICE;   // why the last failed call failed
+    std::string msg;
+
+    double now() { return now_s(); }
+    bool upload(SchedRequest *sr);
+    int64_t slice(const void *cls, int max_nr);
+    bool launch(int stream, const std::vector<Part> &parts, Handle *h);
+    int query(const Handle &h);
+    void retire(const Handle &h);
 };
 
 }  // namespace
@@ -129,7 +79,6 @@ struct zb_server {
     size_t max_pending = 1024;
 
     char *arena_base = nullptr;
-    Arena arena;
     std::vector<hipStream_t> streams;
     hipStream_t copy = nullptr;
     unsigned long long *queues = nullptr;   // nstreams * depth blocks of MAXSEG
@@ -145,16 +94,9 @@ struct zb_server {
     std::string broken_msg;
 
     uint64_t next_ticket = 1;
-    std::deque<Request *> pending;
-    std::vector<Request *> active;          // admitted, not all zones launched or finished
-    std::map<uint64_t, Request *> all;       // every request not yet fetched
-    std::vector<Launch> inflight;
-    std::vector<int> per_stream;
-
-    // totals
-    uint64_t n_launches = 0, n_done = 0;
-    int64_t zones_done = 0;
-    size_t peak_used = 0;
+    std::map<uint64_t, Request *> all;   // every request not yet fetched
+    Scheduler<HipDev> sched;             // arena, queue, launches in flight, totals
+    HipDev dev;
 };
 
 static int64_t slice_zones(zb_server *S, const KernelInfo *k, int nr)
@@ -167,6 +109,91 @@ static int64_t slice_zones(zb_server *S, const KernelInfo *k, int nr)
     return std::max<int64_t>(cap / 2, 64);
 }
 
+bool HipDev::upload(SchedRequest *sr)
+{
+    Request *r = static_cast<Request *>(sr);
+    char *base = S->arena_base + r->off;
+    const int64_t z = r->zones;
+    size_t o = 0;
+    r->state = (double *)(base + o);
+    o += arena_round(sizeof(double) * r->row * z);
+    r->status = (int32_t *)(base + o);
+    o += arena_round(sizeof(int32_t) * z);
+    r->stats = (zb_zone_stats *)(base + o);
+    o += arena_round(sizeof(zb_zone_stats) * z);
+    r->scale = r->in_scale.empty() ? nullptr : (double *)(base + o);
+    hipError_t e1 = hipMemcpyAsync(r->state, r->in_state.data(), sizeof(double) * r->row * z,
+                                   hipMemcpyHostToDevice, S->copy);
+    hipError_t e2 = r->scale ? hipMemcpyAsync(r->scale, r->in_scale.data(), r->in_scale.size() * sizeof(double),
+                                              hipMemcpyHostToDevice, S->copy)
+                             : hipSuccess;
+    hipError_t e3 = hipEventRecord(r->uploaded, S->copy);
+    return e1 == hipSuccess && e2 == hipSuccess && e3 == hipSuccess;
+}
+
+int64_t HipDev::slice(const void *cls, int max_nr)
+{
+    return slice_zones(S, static_cast<const KernelInfo *>(cls), max_nr);
+}
+
+bool HipDev::launch(int s, const std::vector<Part> &parts, Handle *h)
+{
+    const KernelInfo *k = static_cast<const KernelInfo *>(parts[0].r->cls);
+    std::vector<zb_segment> segs;
+    hipStream_t st = S->streams[s];
+    for (const Part &p : parts) {
+        const Request *r = static_cast<const Request *>(p.r);
+        zb_segment g;
+        g.net = r->net;
+        g.state = r->state + (size_t)p.first * r->row;
+        g.zones = p.n;
+        g.dt = r->dt;
+        g.rtol = r->rtol;
+        g.atol = r->atol;
+        g.rate_scale = r->scale ? r->scale + (size_t)p.first * r->net->dn.nr : nullptr;
+        g.zone_status = r->status + p.first;
+        g.stats = r->stats + p.first;
+        g.source = nullptr;
+        segs.push_back(g);
+        if (hipStreamWaitEvent(st, r->uploaded, 0) != hipSuccess) {
+            err = ZB_EDEVICE;
+            msg = "stream wait failed";
+            return false;
+        }
+    }
+    // one block and one event per launch in flight: nstreams * depth of each exist
+    h->qblock = S->free_qblocks.back();
+    S->free_qblocks.pop_back();
+    h->done = S->free_events.back();
+    S->free_events.pop_back();
+    Workspace ws{S->queues + (size_t)h->qblock * MAXSEG, 1, S->nfail};
+    zb_opts o = S->opts;
+    zb_err e = burn_impl(S->ctx, segs.data(), (int)segs.size(), &o, st, k->lanes, nullptr, &ws);
+    if (e == ZB_OK && hipEventRecord(h->done, st) != hipSuccess) e = ZB_EDEVICE;
+    if (e != ZB_OK) {
+        err = e;
+        msg = "burn launch could not be issued";
+        return false;
+    }
+    return true;
+}
+
+int HipDev::query(const Handle &h)
+{
+    const hipError_t q = hipEventQuery(h.done);
+    if (q == hipErrorNotReady) return 1;
+    if (q == hipSuccess) return 0;
+    err = ZB_EDEVICE;
+    msg = std::string("burn launch failed: ") + hipGetErrorString(q);
+    return -1;
+}
+
+void HipDev::retire(const Handle &h)
+{
+    S->free_qblocks.push_back(h.qblock);
+    S->free_events.push_back(h.done);
+}
+
 static void fail_all(zb_server *S, zb_err e, const std::string &msg)
 {
     S->broken = e;
@@ -177,169 +204,33 @@ static void fail_all(zb_server *S, zb_err e, const std::string &msg)
             kv.second->t_done = now_s();
         }
     }
-    S->pending.clear();
-    S->active.clear();
+    S->sched.pending.clear();
+    S->sched.active.clear();
     S->cv_done.notify_all();
-}
-
-// One pass of the scheduler; called with S->mu held.  Returns true if anything happened.
-static bool schedule_once(zb_server *S, std::unique_lock<std::mutex> &lk)
-{
-    bool any = false;
-    // 1. completions
-    for (size_t i = 0; i < S->inflight.size();) {
-        Launch &L = S->inflight[i];
-        hipError_t q = hipEventQuery(L.done);
-        if (q == hipErrorNotReady) {
-            ++i;
-            continue;
-        }
-        if (q != hipSuccess) {
-            fail_all(S, ZB_EDEVICE, std::string("burn launch failed: ") + hipGetErrorString(q));
-            return true;
-        }
-        const double t = now_s();
-        for (auto &p : L.parts) {
-            Request *r = p.first;
-            r->finished += p.second;
-            if (r->finished == r->zones) {
-                r->st = DONE;
-                r->t_done = t;
-                S->n_done++;
-                S->zones_done += r->zones;
-                S->active.erase(std::find(S->active.begin(), S->active.end(), r));
-                S->cv_done.notify_all();
-            }
-        }
-        S->per_stream[L.stream]--;
-        S->free_qblocks.push_back(L.qblock);
-        S->free_events.push_back(L.done);
-        S->inflight.erase(S->inflight.begin() + i);
-        any = true;
-    }
-    // 2. admission, first come first served
-    while (!S->pending.empty()) {
-        Request *r = S->pending.front();
-        size_t off = 0;
-        if (!S->arena.alloc(r->bytes, &off)) break;
-        S->pending.pop_front();
-        r->off = off;
-        char *base = S->arena_base + off;
-        const int64_t z = r->zones;
-        size_t o = 0;
-        r->state = (double *)(base + o);
-        o += (sizeof(double) * r->row * z + ALIGN - 1) & ~(ALIGN - 1);
-        r->status = (int32_t *)(base + o);
-        o += (sizeof(int32_t) * z + ALIGN - 1) & ~(ALIGN - 1);
-        r->stats = (zb_zone_stats *)(base + o);
-        o += (sizeof(zb_zone_stats) * z + ALIGN - 1) & ~(ALIGN - 1);
-        r->scale = r->in_scale.empty() ? nullptr : (double *)(base + o);
-        S->peak_used = std::max(S->peak_used, S->arena.used());
-        // the upload runs outside the lock (pageable source); the request is not
-        // visible to the launcher until it is queued
-        lk.unlock();
-        hipError_t e1 = hipMemcpyAsync(r->state, r->in_state.data(), sizeof(double) * r->row * z,
-                                       hipMemcpyHostToDevice, S->copy);
-        hipError_t e2 = r->scale ? hipMemcpyAsync(r->scale, r->in_scale.data(), r->in_scale.size() * sizeof(double),
-                                                  hipMemcpyHostToDevice, S->copy)
-                                 : hipSuccess;
-        hipError_t e3 = hipEventRecord(r->uploaded, S->copy);
-        lk.lock();
-        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
-            fail_all(S, ZB_EDEVICE, "upload of a request failed");
-            return true;
-        }
-        r->st = ADMITTED;
-        r->t_admit = now_s();
-        S->active.push_back(r);
-        any = true;
-    }
-    // 3. launches: fill every stream up to `depth` launches in flight
-    for (int s = 0; s < S->nstreams; ++s) {
-        while (S->per_stream[s] < S->depth) {
-            // Shortest remaining work first: the request with the least estimated
-            // work left decides the kernel class, and the launch takes slices of the
-            // requests of that class in the same order.  New small requests thus pass
-            // large ones at launch granularity (mean and median latency), while a large
-            // request still gets every launch slot nobody else needs.
-            std::vector<Request *> cand;
-            for (Request *r : S->active)
-                if (r->next < r->zones) cand.push_back(r);
-            if (cand.empty()) return any;
-            auto left = [](const Request *r) { return (double)(r->zones - r->next) * r->cost; };
-            std::stable_sort(cand.begin(), cand.end(),
-                             [&](const Request *a, const Request *b) { return left(a) < left(b); });
-            const KernelInfo *k = cand[0]->k;
-            int max_nr = 0;
-            for (Request *r : cand)
-                if (r->k == k) max_nr = std::max(max_nr, r->net->dn.nr);
-            const int64_t slice = slice_zones(S, k, max_nr);
-            const int64_t cap = 2 * slice;
-            std::vector<zb_segment> segs;
-            Launch L;
-            int64_t total = 0;
-            for (Request *r : cand) {
-                if ((int)segs.size() >= MAXSEG || total >= cap) break;
-                if (r->k != k) continue;
-                int64_t n = std::min({r->zones - r->next, slice, cap - total});
-                zb_segment g;
-                g.net = r->net;
-                g.state = r->state + (size_t)r->next * r->row;
-                g.zones = n;
-                g.dt = r->dt;
-                g.rtol = r->rtol;
-                g.atol = r->atol;
-                g.rate_scale = r->scale ? r->scale + (size_t)r->next * r->net->dn.nr : nullptr;
-                g.zone_status = r->status + r->next;
-                g.stats = r->stats + r->next;
-                g.source = nullptr;
-                segs.push_back(g);
-                L.parts.push_back({r, n});
-                r->next += n;
-                total += n;
-                if (r->t_first == 0) r->t_first = now_s();
-            }
-            hipStream_t st = S->streams[s];
-            for (auto &p : L.parts) {
-                if (hipStreamWaitEvent(st, p.first->uploaded, 0) != hipSuccess) {
-                    fail_all(S, ZB_EDEVICE, "stream wait failed");
-                    return true;
-                }
-            }
-            L.qblock = S->free_qblocks.back();
-            S->free_qblocks.pop_back();
-            L.done = S->free_events.back();
-            S->free_events.pop_back();
-            L.stream = s;
-            Workspace ws{S->queues + (size_t)L.qblock * MAXSEG, 1, S->nfail};
-            zb_opts o = S->opts;
-            zb_err e = burn_impl(S->ctx, segs.data(), (int)segs.size(), &o, st, k->lanes, nullptr, &ws);
-            if (e == ZB_OK && hipEventRecord(L.done, st) != hipSuccess) e = ZB_EDEVICE;
-            if (e != ZB_OK) {
-                fail_all(S, e, "burn launch could not be issued");
-                return true;
-            }
-            S->per_stream[s]++;
-            S->n_launches++;
-            S->inflight.push_back(std::move(L));
-            any = true;
-        }
-    }
-    return any;
 }
 
 static void server_loop(zb_server *S)
 {
     (void)hipSetDevice(S->ctx->device);
     std::unique_lock<std::mutex> lk(S->mu);
+    std::vector<SchedRequest *> done;
     while (!S->stop) {
-        bool any = S->broken == ZB_OK ? schedule_once(S, lk) : false;
+        bool any = false;
+        if (S->broken == ZB_OK) {
+            done.clear();
+            S->dev.msg.clear();
+            const auto o = S->sched.step(S->dev, lk, done);
+            if (!done.empty()) S->cv_done.notify_all();
+            if (o == Scheduler<HipDev>::FAILED)
+                fail_all(S, S->dev.msg.empty() ? ZB_EDEVICE : S->dev.err,
+                         S->dev.msg.empty() ? S->sched.error : S->dev.msg);
+            any = o != Scheduler<HipDev>::IDLE;
+        }
         if (S->stop) break;
         if (!any) {
             // poll launches in flight often; sleep longer when idle
-            auto wait = S->inflight.empty() ? std::chrono::milliseconds(5) : std::chrono::milliseconds(0);
-            if (S->inflight.empty())
-                S->cv_work.wait_for(lk, wait);
+            if (S->sched.inflight.empty())
+                S->cv_work.wait_for(lk, std::chrono::milliseconds(5));
             else
                 S->cv_work.wait_for(lk, std::chrono::microseconds(100));
         }
@@ -361,7 +252,7 @@ static zb_err server_free(zb_server *S)
         if (kv.second->uploaded) (void)hipEventDestroy(kv.second->uploaded);
         delete kv.second;
     }
-    for (auto &L : S->inflight) (void)hipEventDestroy(L.done);
+    for (auto &L : S->sched.inflight) (void)hipEventDestroy(L.h.done);
     for (auto e : S->free_events) (void)hipEventDestroy(e);
     for (auto s : S->streams) (void)hipStreamDestroy(s);
     if (S->copy) (void)hipStreamDestroy(S->copy);
@@ -419,7 +310,7 @@ extern "C" zb_err zb_server_create(zb_context *ctx, const zb_server_opts *so, zb
         delete S;
         return fail(ZB_ENOMEM, "could not allocate the HBM budget of %zu bytes", (size_t)so->hbm_budget_bytes);
     }
-    S->arena.init(so->hbm_budget_bytes);
+    S->dev.S = S;
     if (hipMalloc((void **)&S->queues, sizeof(unsigned long long) * (MAXSEG * (size_t)nblocks + 1)) != hipSuccess) {
         (void)hipFree(S->arena_base);
         delete S;
@@ -427,7 +318,7 @@ extern "C" zb_err zb_server_create(zb_context *ctx, const zb_server_opts *so, zb
     }
     S->nfail = S->queues + (size_t)MAXSEG * nblocks;
     S->streams.resize(S->nstreams, nullptr);
-    S->per_stream.assign(S->nstreams, 0);
+    S->sched.init(so->hbm_budget_bytes, S->nstreams, S->depth, MAXSEG);
     bool ok = launch_reset(S->nfail, 1, nullptr) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
     for (int i = 0; ok && i < S->nstreams; ++i) ok = hipStreamCreateWithFlags(&S->streams[i], hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&S->copy, hipStreamNonBlocking) == hipSuccess;
@@ -460,16 +351,18 @@ extern "C" zb_err zb_server_submit(zb_server *S, const zb_network *net, const do
     const KernelInfo *k = kernel_for(net->dn.nv, lanes, S->opts.precision == ZB_MIXED,
                                      method_of(&S->opts));
     if (!k) return fail(ZB_EUNSUPPORTED, "no kernel for nv=%d with %d lanes", net->dn.nv, lanes);
-    auto al = [](size_t b) { return (b + ALIGN - 1) & ~(ALIGN - 1); };
+    auto al = arena_round;
     size_t bytes = al(sizeof(double) * row * (size_t)zones) + al(sizeof(int32_t) * (size_t)zones) +
                    al(sizeof(zb_zone_stats) * (size_t)zones) +
                    (host_rate_scale ? al(sizeof(double) * net->dn.nr * (size_t)zones) : 0);
-    if (bytes > S->arena.size())
+    if (bytes > S->sched.arena.size())
         return fail(ZB_EINVAL, "request needs %zu device bytes, more than the whole budget", bytes);
     Request *r = new (std::nothrow) Request();
     if (!r) return fail(ZB_ENOMEM, "host allocation failed");
     r->net = net;
     r->k = k;
+    r->cls = k;
+    r->nr = net->dn.nr;
     r->row = row;
     r->zones = zones;
     r->dt = dt;
@@ -501,13 +394,13 @@ extern "C" zb_err zb_server_submit(zb_server *S, const zb_network *net, const do
             delete r;
             return fail(S->broken, "server stopped: %s", S->broken_msg.c_str());
         }
-        if (S->pending.size() >= S->max_pending) {
+        if (S->sched.pending.size() >= S->max_pending) {
             (void)hipEventDestroy(r->uploaded);
             delete r;
             return fail(ZB_EBUSY, "pending queue full (%zu requests)", S->max_pending);
         }
         r->ticket = S->next_ticket++;
-        S->pending.push_back(r);
+        S->sched.enqueue(r);
         S->all[r->ticket] = r;
         *ticket = r->ticket;
     }
@@ -576,7 +469,7 @@ extern "C" zb_err zb_server_fetch(zb_server *S, uint64_t ticket, double *host_st
     }
     {
         std::lock_guard<std::mutex> lk(S->mu);
-        S->arena.release(r->off, r->bytes);
+        S->sched.release(r);
     }
     S->cv_work.notify_all();   // memory freed: admission may proceed
     (void)hipEventDestroy(r->uploaded);
@@ -588,13 +481,13 @@ extern "C" zb_err zb_server_stats(zb_server *S, zb_server_totals *out)
 {
     if (!S || !out) return fail(ZB_EINVAL, "NULL argument");
     std::lock_guard<std::mutex> lk(S->mu);
-    out->requests_done = (int64_t)S->n_done;
-    out->zones_done = S->zones_done;
-    out->launches = (int64_t)S->n_launches;
-    out->pending = (int64_t)S->pending.size();
-    out->active = (int64_t)S->active.size();
-    out->bytes_in_use = (int64_t)S->arena.used();
-    out->peak_bytes_in_use = (int64_t)S->peak_used;
+    out->requests_done = (int64_t)S->sched.n_done;
+    out->zones_done = S->sched.zones_done;
+    out->launches = (int64_t)S->sched.n_launches;
+    out->pending = (int64_t)S->sched.pending.size();
+    out->active = (int64_t)S->sched.active.size();
+    out->bytes_in_use = (int64_t)S->sched.arena.used();
+    out->peak_bytes_in_use = (int64_t)S->sched.peak_used;
     return ZB_OK;
 }
 

@@ -1,5 +1,6 @@
 """Host-side logic of the runtime built for the CPU alone, under AddressSanitizer and
-UndefinedBehaviorSanitizer (no GPU, no HIP): the context's slot rotation."""
+UndefinedBehaviorSanitizer (no GPU, no HIP): the context's slot rotation and the burn server's
+scheduling policy on a fake device."""
 import os
 import shutil
 import subprocess
@@ -26,3 +27,10 @@ def _build_and_run(src, tmp_path):
 def test_slot_rotation_waits_for_the_previous_user(tmp_path):
     out = _build_and_run("slots_test.cpp", tmp_path)
     assert "slots ok" in out
+
+
+
+def test_server_scheduling_on_a_fake_device(tmp_path):
+    out = _build_and_run("sched_test.cpp", tmp_path)
+    for part in ("arena ok", "plan ok", "simulation ok", "failures ok", "threads ok", "sched ok"):
+        assert part in out
