@@ -260,8 +260,8 @@ typedef struct {
     size_t hbm_budget_bytes;       /* device bytes for resident requests (>= 1 MiB), allocated once */
     int32_t streams;               /* concurrent launch streams, 0 = 4 (1..8) */
     int32_t launches_per_stream;   /* launches queued per stream, 0 = 2 (1..4) */
-    int64_t slice_zones;           /* zones per slice, 0 = half of the GPU's resident zones for
-                                      the request's kernel */
+    int64_t slice_zones;           /* zones per slice, 0 = the GPU's resident zones for the
+                                      request's kernel (a launch holds two slices) */
     int32_t max_pending;           /* requests waiting for admission before ZB_EBUSY, 0 = 1024 */
     int32_t reserved;
     zb_opts burn;                  /* precision, mapping and max_steps of every request */
