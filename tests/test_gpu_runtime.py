@@ -134,6 +134,108 @@ def test_torch_graph_capture_of_zb_burn(zbm):
     net.close()
 
 
+def test_counter_ring_wraps_without_waiting_between_calls(zbm):
+    """1100 calls on one stream with no synchronisation between them: the context's 1024
+    zone-queue slots wrap, and a reused slot is first waited for, so every call's zones come
+    out bitwise as one call over all of them."""
+    zb, _, nets_d, _ = zbm
+    ctx = zb.Context(0)
+    net = zb.Network(ctx, nets_d[0])
+    n, per = 1100, 4
+    st, sc = W.robertson_zones(n * per, seed=77)
+    full = torch.tensor(st, device="cuda:0")
+    fsc = torch.tensor(sc, device="cuda:0")
+    ref_status, ref_stats = zb.burn(ctx, net, full, 1.0e5, 1e-8, 1e-12, rate_scale=fsc)
+    zb.sync(ctx)
+    t = torch.tensor(st, device="cuda:0")
+    outs = [zb.burn(ctx, net, t[i * per:(i + 1) * per], 1.0e5, 1e-8, 1e-12,
+                    rate_scale=fsc[i * per:(i + 1) * per]) for i in range(n)]
+    zb.sync(ctx)
+    assert np.array_equal(t.cpu().numpy(), full.cpu().numpy())
+    assert np.array_equal(torch.cat([o[0] for o in outs]).cpu().numpy(), ref_status.cpu().numpy())
+    assert np.array_equal(torch.cat([o[1] for o in outs]).cpu().numpy(), ref_stats.cpu().numpy())
+    net.close()
+    ctx.close()
+
+
+def test_fallback_list_ring_wraps_without_waiting_between_calls(zbm):
+    """20 mixed-precision calls with the FP64 fallback and no synchronisation between them:
+    the 16 fallback lists of the context wrap, and each call still rescues exactly its own
+    failed zones (bitwise as the same call made alone)."""
+    zb = zbm[0]
+    ctx = zb.Context(0)
+    net_d = W.random_network(7, 12, 881)
+    full = W.random_zones(net_d, 131072, seed=882)
+    net = zb.Network(ctx, net_d)
+    t = torch.tensor(full, device="cuda:0")
+    status, _ = zb.burn(ctx, net, t, 1.0, 1e-8, 1e-12, precision="mixed")
+    zb.sync(ctx)
+    failed = np.nonzero(status.cpu().numpy() != 0)[0]
+    assert failed.size > 0, "the input must have zones that fail in mixed precision"
+    st = full[np.union1d(failed, np.arange(40))]
+    a = torch.tensor(st, device="cuda:0")
+    ref = zb.burn(ctx, net, a, 1.0, 1e-8, 1e-12, precision="mixed", fp64_fallback=True)
+    zb.sync(ctx)
+    assert (ref[0].cpu().numpy() == 7).sum() == failed.size
+    ts = [torch.tensor(st, device="cuda:0") for _ in range(20)]
+    outs = [zb.burn(ctx, net, x, 1.0, 1e-8, 1e-12, precision="mixed", fp64_fallback=True) for x in ts]
+    zb.sync(ctx)
+    for x, o in zip(ts, outs):
+        assert np.array_equal(x.cpu().numpy(), a.cpu().numpy())
+        assert np.array_equal(o[0].cpu().numpy(), ref[0].cpu().numpy())
+        assert np.array_equal(o[1].cpu().numpy(), ref[1].cpu().numpy())
+    net.close()
+    ctx.close()
+
+
+def test_captured_calls_beyond_the_capture_slots_are_refused(zbm):
+    """A call captured into a graph keeps its zone-queue slot for the context's lifetime; the
+    65th captured call of a context is refused with ZB_EBUSY (no kernel is launched), and
+    the captured graphs still replay correctly."""
+    zb, _, nets_d, _ = zbm
+    ctx = zb.Context(0)
+    net = zb.Network(ctx, nets_d[0])
+    st, sc = W.robertson_zones(8, seed=5)
+    state = torch.tensor(st, device="cuda:0")
+    scale = torch.tensor(sc, device="cuda:0")
+    ref_status, _ = zb.burn(ctx, net, state.clone(), 1.0e5, 1e-8, 1e-12, rate_scale=scale)
+    zb.sync(ctx)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        zb.burn(ctx, net, state.clone(), 1.0e5, 1e-8, 1e-12, rate_scale=scale)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graphs, bufs = [], []
+    for i in range(64):
+        buf = state.clone()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            out = zb.burn(ctx, net, buf, 1.0e5, 1e-8, 1e-12, rate_scale=scale)
+        graphs.append((g, buf, out))
+    g = torch.cuda.CUDAGraph()
+    buf = state.clone()
+    with pytest.raises(zb.ZoneburnError) as ei:
+        with torch.cuda.graph(g):
+            zb.burn(ctx, net, buf, 1.0e5, 1e-8, 1e-12, rate_scale=scale)
+    assert ei.value.code == zb.EBUSY
+    torch.cuda.synchronize()
+    for k in (0, 63):
+        gk, bk, ok = graphs[k]
+        bk.copy_(state)
+        torch.cuda.synchronize()
+        gk.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(ok[0].cpu().numpy(), ref_status.cpu().numpy())
+    # eager calls still run
+    x = state.clone()
+    zb.burn(ctx, net, x, 1.0e5, 1e-8, 1e-12, rate_scale=scale)
+    zb.sync(ctx)
+    del graphs
+    net.close()
+    ctx.close()
+
+
 def serving_mix(nets_d, n, seed):
     rng = np.random.default_rng(seed)
     reqs = []
