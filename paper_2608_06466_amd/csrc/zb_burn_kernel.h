@@ -448,12 +448,8 @@ struct Ctx {
     int gl;                  // lane within the group
     double *S;               // group LDS base
     LdsLayout lay;
-    DevNet net;
-    double *state;
-    const double *scale;
-    const double *source;
-    int32_t *status, *stats;
-    double rtol, atol, dt;
+    int seg;                 // the segment worked on (wave-uniform)
+    int ns, nv;              // its network's species and integrated variables
     int64_t zone;
     int jac_policy;
     bool lu_blocked;         // the blocked matrix-core LU (48-row FP32 kernels)
@@ -462,6 +458,35 @@ struct Ctx {
 
 template <int NVP, int L>
 __device__ __forceinline__ int row_of(const Ctx &c, int s) { return c.gl + L * s; }
+
+// The segment's network tables and buffers, read from the kernel-argument segment where
+// they are used.  Held in scalar registers through the persistent loop, they (with the
+// loop's other uniform values) overflowed the scalar register file and were spilled to
+// lanes of vector registers, each reload of the 16-register block costing 16 vector
+// instructions.  The loads hit the scalar cache; the opaque segment index keeps the
+// compiler from hoisting them out of the loop again.
+__device__ __forceinline__ const Segment &seg_of(const Ctx &c)
+{
+    const BurnArgs *pa = (const BurnArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    return pa->seg[own_copy(c.seg)];
+}
+
+__device__ __forceinline__ DevNet net_of(const Ctx &c)
+{
+    const DevNet &n = seg_of(c).net;
+    DevNet r;
+    r.ns = c.ns;
+    r.nv = c.nv;
+    r.thermal = n.thermal;
+    r.nr = n.nr;
+    r.inv_len = n.inv_len;
+    r.rea_len = n.rea_len;
+    r.rct = n.rct;
+    r.par = n.par;
+    r.inv = n.inv;
+    r.rea = n.rea;
+    return r;
+}
 
 // Per-reaction rate factors in LDS, used when the launch has any (rate scales, or the constant
 // rates of a network without temperature); otherwise they are all 1 and neither written nor
@@ -485,13 +510,13 @@ __device__ __forceinline__ double wrms(const Ctx &c, const Zone<NVP, L, LT> &z,
     double s = 0.0;
 #pragma unroll
     for (int k = 0; k < RPL; ++k) {
-        if (row_of<NVP, L>(c, k) < c.net.nv) {
+        if (row_of<NVP, L>(c, k) < c.nv) {
             double x = v[k] * z.iw[k];
             s = fma(x, x, s);
         }
     }
     s = greduce<L>(s, OpAdd());
-    return sqrt(s / (double)c.net.nv);
+    return sqrt(s / (double)c.nv);
 }
 
 // ------------------------------------------------------------- network
@@ -503,7 +528,7 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
                      double (&fo)[Zone<NVP, L, LT>::RPL])
 {
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
-    const DevNet &N = c.net;
+    const DevNet N = net_of(c);
     double *ybuf = c.S + c.lay.ybuf;
     double *ks = c.S + c.lay.ks;
     double *rx = c.S + c.lay.rx;
@@ -706,7 +731,7 @@ __device__ __forceinline__ void fd_jacobian(const Ctx &c, Zone<NVP, L, LT> &z,
     using JT = JacT<NVP, LT>;
     JT *jb = (JT *)(c.S + c.lay.jbuf);
     eval<false>(c, z, yv, fo);
-    const int nv = c.net.nv;
+    const int nv = c.nv;
     for (int j = 0; j < nv; ++j) {
         double yp[RPL], fp[RPL];
         double dj = 0.0;
@@ -742,7 +767,7 @@ __device__ __forceinline__ void form_M(const Ctx &c, Zone<NVP, L, LT> &z, double
 {
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
     constexpr int JS = NVP + 1;
-    const DevNet &N = c.net;
+    const DevNet N = net_of(c);
     const JacT<NVP, LT> *jb = (const JacT<NVP, LT> *)(c.S + c.lay.jbuf);
     lds_fence();
     constexpr bool MIXED = sizeof(LT) == 4;
@@ -826,7 +851,7 @@ __device__ __forceinline__ void lu_factor_blocked(const Ctx &c, Zone<NVP, L, LT>
     float *const AT = UT + PB * SU;                    // 32 x SA: multipliers of unpivoted rows
     float *const LW = AT + 32 * SA;                    // 16 x SL: the panel's lower triangle
     float *const DT = AT;                              // 32 x SD: the product (AT, LW read by then)
-    const int nv = own_copy(c.net.nv);
+    const int nv = own_copy(c.nv);
     const int lane = c.gl;
     z.pstep[0] = 127;
     z.pivlane = lane;
@@ -986,7 +1011,7 @@ __device__ __forceinline__ void lu_factor(const Ctx &c, Zone<NVP, L, LT> &z)
     }
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
     LT *prow = (LT *)(c.S + c.lay.prow);
-    const int nv = own_copy(c.net.nv);
+    const int nv = own_copy(c.nv);
     sfor<0, RPL>([&](auto S) { z.pstep[S] = 127; });
     z.pivlane = c.gl;
     // The steps run in chunks of 8 (steps8); lanes past nvp hold zero rows and never pivot.
@@ -1113,7 +1138,7 @@ __device__ __forceinline__ void lu_solve(const Ctx &c, const Zone<NVP, L, LT> &z
 {
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
     constexpr bool MIXED = sizeof(LT) == 4;
-    const int nv = own_copy(c.net.nv);
+    const int nv = own_copy(c.nv);
     if constexpr (RPL == 1) {
         // rows in pivot order (lu_factor): row k of L\U is in group lane k
         const int src = (int)(threadIdx.x & (64 - L)) + z.pivlane;
@@ -1204,8 +1229,8 @@ __device__ __forceinline__ void set_weights(const Ctx &c, Zone<NVP, L, LT> &z)
     for (int s = 0; s < RPL; ++s) {
         int i = row_of<NVP, L>(c, s);
         double w = z.atol + z.rtol * fabs(z.Z[0][s]);
-        z.iw[s] = (i < c.net.nv) ? 1.0 / w : 0.0;
-        if (i < NVP) wb[i] = (i < c.net.nv) ? w : 1.0;
+        z.iw[s] = (i < c.nv) ? 1.0 / w : 0.0;
+        if (i < NVP) wb[i] = (i < c.nv) ? w : 1.0;
     }
 }
 
@@ -1263,12 +1288,14 @@ template <bool VC, int NVP, int L, class LT>
 __device__ __forceinline__ int zone_start(const Ctx &c, Zone<NVP, L, LT> &z)
 {
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
-    const DevNet &N = c.net;
-    const double *row = c.state + c.zone * (N.ns + 1);
+    const DevNet N = net_of(c);
+    const Segment &SG = seg_of(c);
+    const double *row = SG.state + c.zone * (N.ns + 1);
+    const double *scale = SG.scale, *source = SG.source;
     double *ks = c.S + c.lay.ks;
     if (rates_in_lds<NVP, L, LT>(c)) {
         for (int r = c.gl; r < N.nr; r += L) {
-            double s = c.scale ? c.scale[c.zone * N.nr + r] : 1.0;
+            double s = scale ? scale[c.zone * N.nr + r] : 1.0;
             ks[r] = N.thermal ? s : s * exp(N.par[r].x);
         }
     }
@@ -1277,7 +1304,7 @@ __device__ __forceinline__ int zone_start(const Ctx &c, Zone<NVP, L, LT> &z)
     for (int s = 0; s < RPL; ++s) {
         int i = row_of<NVP, L>(c, s);
         double v = (i < N.nv) ? row[i] : 0.0;
-        z.src[s] = (c.source && i < N.nv) ? c.source[c.zone * (N.ns + 1) + i] : 0.0;
+        z.src[s] = (source && i < N.nv) ? source[c.zone * (N.ns + 1) + i] : 0.0;
         if (!isfinite(v) || !isfinite(z.src[s])) bad = true;
 #pragma unroll
         for (int j = 0; j <= QMAX; ++j) z.Z[j][s] = 0.0;
@@ -1312,7 +1339,7 @@ __device__ __forceinline__ int zone_start(const Ctx &c, Zone<NVP, L, LT> &z)
     double d2 = wrms(c, z, y1) / ha;
     double dm = fmax(d1, d2);
     double hb = (dm <= 1e-15) ? fmax(1e-6, ha * 1e-3) : sqrt(0.01 / dm);
-    double h = fmin(fmin(100.0 * ha, hb), c.dt);
+    double h = fmin(fmin(100.0 * ha, hb), seg_of(c).dt);
     if (!isfinite(h) || !(h > 0.0)) return ZB_ZONE_NONFINITE;
     z.h = h;
     z.t = 0.0;
@@ -1426,10 +1453,10 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
     const double tau = 0.03;
     if (z.nst >= z.max_steps) return ZB_ZONE_MAXSTEPS;
     bool last = false;
-    if (z.t + z.h >= c.dt * (1.0 - 4.0 * DBL_EPSILON)) {
-        double eta = (c.dt - z.t) / z.h;
+    if (z.t + z.h >= seg_of(c).dt * (1.0 - 4.0 * DBL_EPSILON)) {
+        double eta = (seg_of(c).dt - z.t) / z.h;
         rescale(z, eta);
-        z.h = c.dt - z.t;
+        z.h = seg_of(c).dt - z.t;
         z.nequal = 0;
         last = true;
     }
@@ -1510,7 +1537,7 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
 #pragma unroll
         for (int s = 0; s < RPL; ++s) {
             const int i = row_of<NVP, L>(c, s);
-            if (i < c.net.ns && z.y[s] < -z.atol) {
+            if (i < c.ns && z.y[s] < -z.atol) {
                 const double old = zs[zs_slot<NVP, L, RPL, LT>(c.gl, 0, s)];   // Z_0 before the prediction
                 feas = fmin(feas, (old + z.atol) / (old - z.y[s]));
             }
@@ -1577,7 +1604,7 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
     }
 #pragma unroll
     for (int s = 0; s < RPL; ++s) z.Z[0][s] = z.y[s];
-    z.t = last ? c.dt : z.t + h;
+    z.t = last ? seg_of(c).dt : z.t + h;
     z.nst++;
     z.nequal++;
     z.nefc = z.ncfc = 0;
@@ -1679,12 +1706,12 @@ __device__ __forceinline__ int zone_attempt_rkc(const Ctx &c, Zone<NVP, L, LT> &
 {
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
     constexpr int JS = NVP + 1;
-    const DevNet &N = c.net;
+    const DevNet N = net_of(c);
     if (z.nst >= z.max_steps) return ZB_ZONE_MAXSTEPS;
     bool last = false;
     double h = z.h;
-    if (z.t + h >= c.dt * (1.0 - 4.0 * DBL_EPSILON)) {
-        h = c.dt - z.t;
+    if (z.t + h >= seg_of(c).dt * (1.0 - 4.0 * DBL_EPSILON)) {
+        h = seg_of(c).dt - z.t;
         last = true;
     }
     // spectral-radius bound: max over rows of sum_j |J_ij|
@@ -1792,7 +1819,7 @@ __device__ __forceinline__ int zone_attempt_rkc(const Ctx &c, Zone<NVP, L, LT> &
         z.Z[0][s] = Y1[s];
         z.Z[1][s] = F[s];
     }
-    z.t = last ? c.dt : z.t + h;
+    z.t = last ? seg_of(c).dt : z.t + h;
     z.nst++;
     if (last) return ZB_ZONE_OK;
     z.h = h * fac;
@@ -1804,7 +1831,7 @@ __device__ __forceinline__ int zone_attempt_rkc(const Ctx &c, Zone<NVP, L, LT> &
 template <int NVP, int L, class LT>
 __device__ __forceinline__ void write_stats(const Ctx &c, const Zone<NVP, L, LT> &z, bool add_row)
 {
-    int32_t *o = c.stats + c.zone * 7;
+    int32_t *o = seg_of(c).stats + c.zone * 7;
     int add[7] = {0, 0, 0, 0, 0, 0, 0};
     if (z.tries > 0) {
         const int *cnt = (const int *)(c.S + c.lay.cnt);
@@ -1831,7 +1858,7 @@ __device__ __forceinline__ bool zone_defer(const Ctx &c, const Zone<NVP, L, LT> 
     if (idx >= (unsigned long long)FB_CAP) return false;
     if (c.gl == 0) {
         A.fb[MAXSEG + seg * FB_CAP + idx] = (unsigned long long)c.zone;
-        if (c.stats) write_stats(c, z, false);
+        if (seg_of(c).stats) write_stats(c, z, false);
     }
     return true;
 }
@@ -1840,20 +1867,21 @@ template <int NVP, int L, class LT>
 __device__ __forceinline__ void zone_finish(const Ctx &c, Zone<NVP, L, LT> &z, int status, const BurnArgs &A)
 {
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
-    const int ns = c.net.ns;
+    const int ns = c.ns;
     const bool replay = A.fb_mode == 2;
     if (replay && (status == ZB_ZONE_OK || status == ZB_ZONE_OK_RETRY)) status = ZB_ZONE_OK_FP64;
     if (status != ZB_ZONE_NONFINITE) {
-        double *row = c.state + c.zone * (ns + 1);
+        double *row = seg_of(c).state + c.zone * (ns + 1);
 #pragma unroll
         for (int s = 0; s < RPL; ++s) {
             int i = row_of<NVP, L>(c, s);
-            if (i < c.net.nv) row[i] = z.Z[0][s];
+            if (i < c.nv) row[i] = z.Z[0][s];
         }
     }
     if (c.gl == 0) {
-        if (c.status) c.status[c.zone] = status;
-        if (c.stats) write_stats(c, z, replay);
+        int32_t *st = seg_of(c).status;
+        if (st) st[c.zone] = status;
+        if (seg_of(c).stats) write_stats(c, z, replay);
         if (status != ZB_ZONE_OK && status != ZB_ZONE_OK_RETRY && status != ZB_ZONE_OK_FP64)
             atomicAdd(A.nfail, 1ull);
     }
@@ -1886,24 +1914,9 @@ __device__ __forceinline__ void load_segment(Ctx &c, const BurnArgs &A, int seg,
     // seg is wave-uniform: scalar loads from the kernel-argument segment
     const BurnArgs *pa = (const BurnArgs *)__builtin_amdgcn_kernarg_segment_ptr();
     const Segment &S = pa->seg[__builtin_amdgcn_readfirstlane(seg)];
-    c.net.ns = uniform(S.net.ns);
-    c.net.nv = uniform(S.net.nv);
-    c.net.thermal = uniform(S.net.thermal);
-    c.net.nr = uniform(S.net.nr);
-    c.net.inv_len = uniform(S.net.inv_len);
-    c.net.rea_len = uniform(S.net.rea_len);
-    c.net.rct = uniform(S.net.rct);
-    c.net.par = uniform(S.net.par);
-    c.net.inv = uniform(S.net.inv);
-    c.net.rea = uniform(S.net.rea);
-    c.state = uniform(S.state);
-    c.scale = uniform(S.scale);
-    c.source = uniform(S.source);
-    c.status = uniform(S.status);
-    c.stats = uniform(S.stats);
-    c.rtol = uniform(S.rtol);
-    c.atol = uniform(S.atol);
-    c.dt = uniform(S.dt);
+    c.seg = __builtin_amdgcn_readfirstlane(seg);
+    c.ns = uniform(S.net.ns);
+    c.nv = uniform(S.net.nv);
     c.rates = pa->rates_lds != 0;
     c.lay = lds_layout(nvp, L, rpl, A.max_nr, vc, jf32, c.rates);
 }
@@ -1966,8 +1979,8 @@ void burn_kernel(BurnArgs A)
                 dry = true;
             } else {
                 c.zone = A.fb_mode == 2 ? (int64_t)A.fb[MAXSEG + seg * FB_CAP + item] : (int64_t)item;
-                z.rtol = c.rtol;
-                z.atol = c.atol;
+                z.rtol = seg_of(c).rtol;
+                z.atol = seg_of(c).atol;
                 z.max_steps = A.max_steps;
                 z.tries = 0;
                 z.fdj = 0;
