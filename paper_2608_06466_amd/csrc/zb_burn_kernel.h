@@ -547,7 +547,7 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
         const int i0 = row_of<NVP, L>(c, 0);
         const int4 *l0 = (const int4 *)(N.inv + (i0 < N.ns ? i0 : 0) * N.inv_len);
         sfor<0, PMAX>([&](auto P) {
-            pre[P] = make_int4(-1, 0, -1, 0);
+            pre[P] = make_int4(0, 0, 0, 0);
             if (use_pre && P < n2) pre[P] = gload(l0 + P);
         });
     }
@@ -636,10 +636,11 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
             // A pair of entries: the second is taken under a predicate (a padding entry
             // reads slot 0 and adds nothing), so the LDS reads of both go out together.
             auto pair = [&](int4 en) {
-                const bool has1 = en.z >= 0;
+                const int n0 = en.x >> 16, n1 = en.z >> 16;   // nu; 0 on a padding entry
+                const bool has1 = n1 != 0;
                 const int r0 = en.x & 0xffff, r1 = has1 ? (en.z & 0xffff) : 0;
-                const double nu0 = (double)((en.x >> 16) - 8);
-                const double nu1 = (double)((en.z >> 16) - 8);
+                const double nu0 = (double)n0;
+                const double nu1 = (double)n1;
                 const double w0 = rx[r0], w1 = rx[r1];
                 double p0 = 0.0, p1 = 0.0, q0 = 0.0, q1 = 0.0, t0 = 0.0, t1 = 0.0;
                 if (WANTJ) {
@@ -659,18 +660,18 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
                 }
             };
             if (use_pre) {
-                // entries past the row's list are padding (x < 0), skipped
+                // entries past the row's list are padding (nu = 0), skipped
                 sfor<0, (PMAX > 0 ? PMAX : 1)>([&](auto P) {
-                    if (P < n2 && pre[P].x >= 0) pair(pre[P]);
+                    if (P < n2 && (pre[P].x >> 16) != 0) pair(pre[P]);
                 });
             } else {
-                int4 nen = n2 > 0 ? gload(lst) : make_int4(-1, 0, -1, 0);
+                int4 nen = n2 > 0 ? gload(lst) : make_int4(0, 0, 0, 0);
                 for (int e = 0; e < n2; ++e) {
                     const int4 en = nen;
                     if (e + 1 < n2) nen = gload(lst + e + 1);
-                    if (en.x < 0) break;
+                    if ((en.x >> 16) == 0) break;
                     pair(en);
-                    if (en.z < 0) break;
+                    if ((en.z >> 16) == 0) break;
                 }
             }
             if (WANTJ && N.thermal) {

@@ -160,7 +160,7 @@ extern "C" zb_err zb_network_create(zb_context *ctx, const zb_network_desc *d, z
         memcpy(&qb, &par[r].w, sizeof qb);
         for (int i = 0; i < ns; ++i) {
             int nu = (x.z == i) + (x.w == i) - (x.x == i) - (x.y == i);
-            if (nu != 0) inv[i].push_back(make_int2(r | ((nu + 8) << 16), x.x | ((x.y + 1) << 8)));
+            if (nu != 0) inv[i].push_back(make_int2(r | (int)((unsigned)nu << 16), x.x | ((x.y + 1) << 8)));
             int fl = (x.x == i ? 1 : 0) | (x.y == i ? 2 : 0);
             if (fl) rea[i].push_back(make_int4(r | (fl << 16), 0, (int)(qb & 0xffffffffu), (int)(qb >> 32)));
         }
@@ -172,7 +172,7 @@ extern "C" zb_err zb_network_create(zb_context *ctx, const zb_network_desc *d, z
     }
     inv_len += inv_len & 1;   // even: the kernels take two entries per iteration
     rea_len += rea_len & 1;
-    std::vector<int2> invf((size_t)ns * inv_len, make_int2(-1, 0));
+    std::vector<int2> invf((size_t)ns * inv_len, make_int2(0, 0));   // nu = 0 pads a row
     std::vector<int4> reaf((size_t)ns * rea_len, make_int4(-1, 0, 0, 0));
     for (int i = 0; i < ns; ++i) {
         std::copy(inv[i].begin(), inv[i].end(), invf.begin() + (size_t)i * inv_len);

@@ -14,9 +14,10 @@ constexpr int RMAX = 4096;   // largest number of reactions
 //  rct[r] = (a, b, c, d): reactants a, b and products c, d (-1 when absent).
 //  par[r] = (lnA, n, E, q).
 //  inv[i][e], for every reaction r whose net stoichiometry nu_ir in species i is
-//              non-zero: .x = r | (nu_ir + 8) << 16, .y = a_r | (b_r + 1) << 8
-//              (the reactant columns the row's Jacobian entries go to, so no
-//              second lookup is needed); .x = -1 pads the row.
+//              non-zero: .x = r | nu_ir << 16 (nu_ir a signed 16-bit field, read with
+//              an arithmetic shift), .y = a_r | (b_r + 1) << 8 (the reactant columns
+//              the row's Jacobian entries go to, so no second lookup is needed);
+//              entries with nu = 0 (.x = 0) pad the row.
 //  rea[j][e], for every reaction with species j as a reactant: .x = r | flags << 16
 //              (flag 1: j is the first reactant, 2: the second), .zw = the bits of
 //              q_r; .x = -1 pads the row.
