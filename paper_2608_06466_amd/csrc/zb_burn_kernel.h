@@ -37,6 +37,8 @@
 #include <utility>
 
 #include "zb_internal.h"
+#include "zb_log.h"
+#include "zb_stepmath.h"
 #include "zoneburn.h"
 
 namespace zb {
@@ -344,6 +346,46 @@ __device__ __forceinline__ bool gany(bool b)
 // variable-coefficient BDF with either Jacobian policy.
 constexpr int RKC_SMAX = 250;
 
+// ------------------------------------------------------------- step control
+// The WRMS norms and the step-size factors start from the hardware approximations
+// (v_rcp_f64, v_sqrt_f64, the FP32 log2 and exp2) and are refined by Newton steps to about
+// 1 ulp, so the step sizes and accept/reject decisions agree with the exact formulas as
+// closely as the library routines would: about 15 instructions for a norm against ~36 for
+// a division and a correctly rounded square root, about 50 for a factor against ~180 for a
+// pow and a division.
+
+// Root mean square from a sum of n squares (0, +inf and NaN keep their meaning).
+__device__ __forceinline__ double rms_of_sum(double s, int n)
+{
+    const double dn = (double)n;
+    const double x = s * zbm::recip_from(dn, __builtin_amdgcn_rcp(dn));
+    const double y0 = __builtin_amdgcn_sqrt(x);
+    const double y = zbm::sqrt_from(x, y0, __builtin_amdgcn_rcp(y0));
+    return (x > 0.0 && x < __builtin_inf()) ? y : y0;
+}
+
+// x^(1/k) for x >= 0 (or NaN) and 1 <= k <= 6, as pow(x, 1/k) gives it.  x = 2^(k j) xs
+// with j from the exponent of x, so that xs lies within a few powers of two of 1 and the
+// FP32 start is in range for every positive double; the root is 2^j xs^(1/k), the scalings
+// exact.
+__device__ __forceinline__ double kth_root(double x, int k)
+{
+    const float rk = __builtin_amdgcn_rcpf((float)k);
+    const int j = (int)((float)__builtin_amdgcn_frexp_exp(x) * rk);
+    const double xs = __builtin_amdgcn_ldexp(x, -k * j);
+    const double y0 = (double)__builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)xs) * rk);
+    const double y = __builtin_amdgcn_ldexp(
+        zbm::root_from(xs, k, y0, [](double d) { return __builtin_amdgcn_rcp(d); }), j);
+    return (x > 0.0 && x < __builtin_inf()) ? y : x;   // 0, +inf and NaN pass through
+}
+
+// Step-size factor 1 / (x^(1/k) + 1e-6) of the error and order tests, x = b E >= 0.
+__device__ __forceinline__ double step_factor(double x, int k)
+{
+    const double d = kth_root(x, k) + 1e-6;
+    return (d < __builtin_inf()) ? zbm::recip_from(d, __builtin_amdgcn_rcp(d)) : 1.0 / d;
+}
+
 // --------------------------------------------------------- BDF coefficients
 
 // l_j(q): coefficients of prod_{i<=q} (1 + x/i) divided by H_q (so l_1 = 1).
@@ -516,7 +558,7 @@ __device__ __forceinline__ double wrms(const Ctx &c, const Zone<NVP, L, LT> &z,
         }
     }
     s = greduce<L>(s, OpAdd());
-    return sqrt(s / (double)c.nv);
+    return rms_of_sum(s, c.nv);
 }
 
 // ------------------------------------------------------------- network
@@ -570,7 +612,7 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
     double lnT = 0.0, iT = 0.0;
     if (N.thermal) {
         double T = ybuf[N.ns];
-        lnT = log(T);
+        lnT = zbm::log_series(T);
         iT = 1.0 / T;
     }
     double sT = 0.0, sTT = 0.0;
@@ -1549,7 +1591,7 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
         restore_history(c, z);
         z.netf++;
         if (++z.nefc >= 10) return ZB_ZONE_ERRTEST;
-        double eta = err > 1.0 ? fmax(0.1, 1.0 / (pow(6.0 * err, 1.0 / (double)(z.q + 1)) + 1e-6)) : 1.0;
+        double eta = err > 1.0 ? fmax(0.1, step_factor(6.0 * err, z.q + 1)) : 1.0;
         if (feas < 1.0) eta = fmin(eta, fmax(0.1, 0.9 * feas));
         if (z.nefc >= 3) eta = 0.1;
         z.h *= eta;
@@ -1643,13 +1685,13 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
         }
         double best = 0.0;
         int qnew = q;
-        if (may) best = 1.0 / (pow(6.0 * err, 1.0 / (double)(q + 1)) + 1e-6);
+        if (may) best = step_factor(6.0 * err, q + 1);
         if (may && q > 1) {
-            double etam = 1.0 / (pow(6.0 * Em, 1.0 / (double)q) + 1e-6);
+            double etam = step_factor(6.0 * Em, q);
             if (etam > best) { best = etam; qnew = q - 1; }
         }
         if (may && q < QMAX) {
-            double etap = 1.0 / (pow(10.0 * Ep, 1.0 / (double)(q + 2)) + 1e-6);
+            double etap = step_factor(10.0 * Ep, q + 2);
             if (etap > best) { best = etap; qnew = q + 1; }
         }
         if (best >= 1.5) {
@@ -1802,10 +1844,12 @@ __device__ __forceinline__ int zone_attempt_rkc(const Ctx &c, Zone<NVP, L, LT> &
                 feas = fmin(feas, (z.Z[0][s] + z.atol) / (z.Z[0][s] - Y1[s]));
         }
     }
-    double err = sqrt(greduce<L>(se, OpAdd()) / (double)N.nv);
+    double err = rms_of_sum(greduce<L>(se, OpAdd()), N.nv);
     feas = greduce<L>(feas, OpMin());
     if (!isfinite(err)) err = 1e10;
-    double fac = fmin(10.0, fmax(0.1, 0.8 * pow(err, -1.0 / 3.0)));
+    // 0.8 err^(-1/3) (err finite and >= 0 here; err = 0 gives the cap)
+    const double cr = kth_root(err, 3);
+    double fac = fmin(10.0, fmax(0.1, cr > 0.0 ? 0.8 * zbm::recip_from(cr, __builtin_amdgcn_rcp(cr)) : 10.0));
     if (err > 1.0 || feas < 1.0) {
         z.netf++;
         if (++z.nefc >= 10) return ZB_ZONE_ERRTEST;

@@ -1,6 +1,7 @@
 """Host-side logic of the runtime built for the CPU alone, under AddressSanitizer and
-UndefinedBehaviorSanitizer (no GPU, no HIP): the context's slot rotation and the burn server's
-scheduling policy on a fake device."""
+UndefinedBehaviorSanitizer (no GPU, no HIP): the context's slot rotation, the burn server's
+scheduling policy on a fake device, the series logarithm of the rate evaluation and the
+refinements of the step control."""
 import os
 import shutil
 import subprocess
@@ -34,3 +35,13 @@ def test_server_scheduling_on_a_fake_device(tmp_path):
     out = _build_and_run("sched_test.cpp", tmp_path)
     for part in ("arena ok", "plan ok", "simulation ok", "failures ok", "threads ok", "sched ok"):
         assert part in out
+
+
+def test_series_logarithm_is_within_1_2_ulp(tmp_path):
+    out = _build_and_run("log_test.cpp", tmp_path)
+    assert "log ok" in out
+
+
+def test_step_control_refinements_are_within_1_ulp(tmp_path):
+    out = _build_and_run("stepmath_test.cpp", tmp_path)
+    assert "stepmath ok" in out
