@@ -423,9 +423,11 @@ def robertson(args):
 
 def batched(args, sub=False):
     """Four networks (nv 3, 14, 22, 48; 4:2:1:1 of 2^21 zones) in one zb_burn_batch call, FP64
-    and with the FP32 LU, each against the oracle on a stratified sample; the FP32 run again
-    with the blocked matrix-core LU (lu='mfma': the 48-variable class).  sub: one timed
-    launch per leg, returned as a dict (the headline run's 'batched' object)."""
+    and with the FP32 LU, each against the oracle on a stratified sample.  The FP32 headline
+    takes the autotuned (lanes, LU) pair of each network (lu='auto'); it runs again with the
+    vector LU everywhere (lu='valu') and with the blocked matrix-core LU (lu='mfma': the
+    48-variable class).  sub: one timed launch per leg, returned as a dict (the headline run's
+    'batched' object)."""
     import torch
     import oracle
     from paper_2608_06466_amd import workloads as W
@@ -447,8 +449,9 @@ def batched(args, sub=False):
         for w, i0 in zip(work, init):
             w.copy_(i0)
 
-    # autotuned zone-to-wavefront mapping: each network's lanes per zone, per precision, timed
-    # on 8192 zones drawn from its own segment (zb_autotune; the chosen mapping then serves
+    # autotuned zone-to-wavefront mapping: each network's lanes per zone (and, with the FP32
+    # LU, the factorisation: vector or matrix-core), per precision, timed on 8192 zones drawn
+    # from its own segment (zb_autotune, zb_autotune_candidates; the chosen pair then serves
     # every launch of that network in this context)
     tuned = {}
     rng_t = np.random.default_rng(99)
@@ -457,16 +460,23 @@ def batched(args, sub=False):
             nz = s["state"].shape[0]
             pick = np.sort(rng_t.choice(nz, min(nz, 8192), replace=False))
             sample = torch.tensor(s["state"][pick], device="cuda:0")
-            best, tt = zb.autotune(ctx, nets[k], sample, s["dt"], s["rtol"], s["atol"], prec)
-            tuned.setdefault(f"nv{nets[k].nv}", {})[prec] = {
-                "lanes": best, "ms_per_lane_count_1_to_64": [round(t, 2) for t in tt]}
-            print(f"[bench] batched autotune nv{nets[k].nv} {prec}: lanes {best}", file=sys.stderr,
-                  flush=True)
+            if prec == "fp64":
+                best, tt = zb.autotune(ctx, nets[k], sample, s["dt"], s["rtol"], s["atol"], prec)
+                t = {"lanes": best, "ms_per_lane_count_1_to_64": [round(v, 2) for v in tt]}
+            else:
+                cands, bi = zb.autotune_candidates(ctx, nets[k], sample, s["dt"], s["rtol"],
+                                                   s["atol"], prec)
+                t = {"lanes": cands[bi]["lanes"], "lu": cands[bi]["lu"],
+                     "candidates_ms": {f"{c['lanes']}/{c['lu']}": round(c["ms"], 2)
+                                       for c in cands if c["ms"] > 0}}
+            tuned.setdefault(f"nv{nets[k].nv}", {})[prec] = t
+            print(f"[bench] batched autotune nv{nets[k].nv} {prec}: lanes {t['lanes']}"
+                  f"{' lu ' + t['lu'] if 'lu' in t else ''}", file=sys.stderr, flush=True)
             del sample
 
     res = {}
-    for key, prec, lu in (("fp64", "fp64", "valu"), ("mixed", "mixed", "valu"),
-                          ("mixed_mfma", "mixed", "mfma")):
+    for key, prec, lu in (("fp64", "fp64", "valu"), ("mixed", "mixed", "auto"),
+                          ("mixed_valu", "mixed", "valu"), ("mixed_mfma", "mixed", "mfma")):
         def launch(prec=prec, lu=lu):
             zb.burn_batch(ctx, segs, precision=prec, lu=lu)
             return lambda: zb.sync(ctx)
@@ -501,7 +511,7 @@ def batched(args, sub=False):
     if not args.no_cpu:
         threads = oracle_threads()
         rng = np.random.default_rng(4321)
-        acc = {"fp64": [], "mixed": [], "mixed_mfma": []}
+        acc = {"fp64": [], "mixed": [], "mixed_valu": [], "mixed_mfma": []}
         cpu_time_per_zone = []
         for k, s in enumerate(segs_h):
             nz = s["state"].shape[0]
@@ -531,20 +541,24 @@ def batched(args, sub=False):
                          "rate extrapolated from the per-class time per zone"}
     else:
         cpu = None
-    m, f, b = res["mixed"], res["fp64"], res["mixed_mfma"]
+    m, f, b, v = res["mixed"], res["fp64"], res["mixed_mfma"], res["mixed_valu"]
     val = {k: r["ok"] * within[k] / r["wall_s"] for k, r in res.items()}
     out = {"value": round(val["mixed"], 1), "unit": "zone-burns/s",
            "ms_per_step": round(m["wall_s"] * 1e3, 2), "kernel_ms": round(m["kernel_ms"], 2),
            "steps": steps, "warmup": warmup,
            "workload": f"Robertson : nv14 : nv22 : nv48 = 4:2:1:1 of {total} zones, T log-uniform on "
                        "[90, 2500] K, dt 1 (Robertson 1e5), rtol 1e-8, atol 1e-12, one zb_burn_batch "
-                       "call (mixed precision), zone-to-wavefront mapping autotuned per network",
+                       "call (mixed precision), zone-to-wavefront mapping and LU autotuned per "
+                       "network",
            "per_class": per_class, "autotuned_mapping": tuned, "roofline": roof(m),
            "plain_fp64": {"value": round(val["fp64"], 1), "ms_per_step": round(f["wall_s"] * 1e3, 2),
                           "roofline": roof(f)},
            "mixed_over_fp64": round(val["mixed"] / val["fp64"], 3),
+           "valu_lu": {"value": round(val["mixed_valu"], 1), "ms_per_step": round(v["wall_s"] * 1e3, 2),
+                       "note": "mixed precision with lu='valu': every class factors on the "
+                               "vector units"},
            "mfma_lu": {"value": round(val["mixed_mfma"], 1), "ms_per_step": round(b["wall_s"] * 1e3, 2),
-                       "over_valu_lu": round(val["mixed_mfma"] / val["mixed"], 3),
+                       "over_valu_lu": round(val["mixed_mfma"] / val["mixed_valu"], 3),
                        "note": "mixed precision with lu='mfma': the 48-variable class factors with "
                                "the blocked LU (trailing updates as FP32 MFMA products), the others "
                                "keep the vector-unit LU"},
@@ -554,7 +568,8 @@ def batched(args, sub=False):
     line = _common_line("zone-burns/s, four networks (nv 3, 14, 22, 48) in one call", out["value"],
                         "zone-burns/s", args, out["ms_per_step"], "f64 (f32 LU)",
                         {"workload": out["workload"], "per_class": per_class})
-    for k in ("kernel_ms", "autotuned_mapping", "roofline", "plain_fp64", "mixed_over_fp64", "mfma_lu", "cpu_baseline",
+    for k in ("kernel_ms", "autotuned_mapping", "roofline", "plain_fp64", "mixed_over_fp64", "valu_lu", "mfma_lu",
+              "cpu_baseline",
               "accuracy_vs_oracle"):
         line[k] = out[k]
     print(json.dumps(line), flush=True)

@@ -82,7 +82,7 @@ enum { ZB_MAP_AUTO = 0 };                          /* zb_opts.mapping: else lane
 enum { ZB_JAC_EVERY_STEP = 0, ZB_JAC_REUSE = 1 };  /* zb_opts.jac_policy */
 enum { ZB_BDF = 0, ZB_RKC = 1, ZB_BDF_VARIABLE = 2 };   /* zb_opts.integrator */
 enum { ZB_RETRY_JAC_ANALYTIC = 0, ZB_RETRY_JAC_FD = 1 };   /* zb_opts.retry_jac */
-enum { ZB_LU_VALU = 0, ZB_LU_MFMA = 1 };           /* zb_opts.lu */
+enum { ZB_LU_VALU = 0, ZB_LU_MFMA = 1, ZB_LU_AUTO = 2 };   /* zb_opts.lu */
 
 typedef struct {
     int32_t max_steps;   /* accepted steps per zone before ZB_ZONE_MAXSTEPS (<= 0: 100000) */
@@ -138,7 +138,11 @@ typedef struct {
                             v_mfma_f32_16x16x4f32).  It needs ZB_MIXED, ZB_JAC_EVERY_STEP and a
                             BDF integrator (else ZB_EINVAL).  It applies to networks of 33 to 48
                             variables on 64 lanes per zone; other mappings keep ZB_LU_VALU.  On
-                            MI355X the two run within 2 % of each other at these sizes. */
+                            MI355X the two run within 2 % of each other at these sizes.
+                            ZB_LU_AUTO (2): per segment, the factorisation and lanes per zone
+                            that zb_autotune timed fastest for its network and precision (with
+                            mapping ZB_MAP_AUTO), where the other options allow ZB_LU_MFMA;
+                            else ZB_LU_VALU and the mapping rules of ZB_LU_VALU. */
     int32_t fp64_fallback;   /* 1: with ZB_MIXED, a zone that fails (after the retry, if on) is
                             burned again from its input in FP64, by the FP64 kernel of its
                             class after the mixed-precision run, with the same options; success
@@ -300,7 +304,7 @@ zb_err zb_server_destroy(zb_server *srv);
 zb_err zb_get_mapping(zb_context *ctx, const zb_network *net, int32_t precision, int32_t *lanes);
 /* Time every supported mapping on a DEVICE sample state [zones][ns+1] (copied, not modified)
    and use the fastest qualifying one for (network size, reactions, precision) on this context
-   from now on.  A mapping qualifies when every sample zone ends with the status the first
+   from now on, with the vector LU (ZB_LU_AUTO then resolves to ZB_LU_VALU as well).  A mapping qualifies when every sample zone ends with the status the first
    mapping gave it and at least 99% of the zones agree with that mapping to a gated relative
    1e-6 (the mappings differ only in the order of reductions).  times_ms (HOST, optional)
    receives one entry per lane count 1,2,4,...,64 (negative when unsupported).  Allocates
@@ -308,6 +312,30 @@ zb_err zb_get_mapping(zb_context *ctx, const zb_network *net, int32_t precision,
 zb_err zb_autotune(zb_context *ctx, const zb_network *net, const double *sample_state,
                    int64_t zones, double dt, double rtol, double atol, int32_t precision,
                    int32_t *best_lanes, float *times_ms);
+
+/* One candidate of zb_autotune_candidates. */
+typedef struct {
+    int32_t lanes;       /* lanes per zone */
+    int32_t lu;          /* ZB_LU_VALU or ZB_LU_MFMA */
+    float ms;            /* burn time of the sample (the second of two runs) */
+    int32_t qualified;   /* 1: statuses equal to the first candidate's, >= 99 % of the zones
+                            within a gated relative 1e-6 of it */
+} zb_tune_candidate;
+
+/* The autotuner over both tuned dimensions: every lanes-per-zone mapping with the vector LU,
+   and, where a matrix-core LU kernel exists for the network (ZB_MIXED, 33 to 48 variables,
+   64 lanes), that LU too; each is timed on the DEVICE sample state [zones][ns+1] (copied, not
+   modified) with the Jacobian every step and the BDF integrator.  The fastest qualifying
+   candidate then serves launches with zb_opts.lu = ZB_LU_AUTO and mapping ZB_MAP_AUTO; the
+   fastest qualifying vector-LU one serves launches with ZB_LU_VALU and ZB_MAP_AUTO (what
+   zb_autotune records).  out (HOST, max_out entries, optional) receives the candidates in the
+   order tried, *n_out their number and *best (optional) the index of the chosen one.
+   ZB_EUNSUPPORTED when no candidate ran.  Allocates device scratch for one copy of the
+   sample; synchronous. */
+zb_err zb_autotune_candidates(zb_context *ctx, const zb_network *net, const double *sample_state,
+                              int64_t zones, double dt, double rtol, double atol,
+                              int32_t precision, zb_tune_candidate *out, int32_t max_out,
+                              int32_t *n_out, int32_t *best);
 
 /* Human-readable name of an error code and the last error message of this thread. */
 const char *zb_strerror(zb_err err);

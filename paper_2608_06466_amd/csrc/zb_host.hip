@@ -286,12 +286,41 @@ const KernelInfo *zbh::find_kernel(int nv, int lanes, int mixed, int jac)
     return best;
 }
 
+// ZB_LU_AUTO: the tuned LU where the options allow the matrix-core one (FP32 LU, Jacobian
+// every step, a BDF integrator, the tuned lanes), else the vector LU.
+int zbh::lu_for(zb_context *ctx, const zb_network *net, int prec, const zb_opts *o)
+{
+    if (!o) return ZB_LU_VALU;
+    if (o->lu != ZB_LU_AUTO) return o->lu;
+    if (prec != ZB_MIXED || o->integrator == ZB_RKC || o->jac_policy != ZB_JAC_EVERY_STEP)
+        return ZB_LU_VALU;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (auto &t : ctx->tuned)
+        if (t.nv == net->dn.nv && t.nr == net->dn.nr && t.prec == prec)
+            return (t.auto_lu == ZB_LU_MFMA &&
+                    (o->mapping == ZB_MAP_AUTO || o->mapping == t.auto_lanes))
+                       ? ZB_LU_MFMA
+                       : ZB_LU_VALU;
+    return ZB_LU_VALU;
+}
+
+zb_opts zbh::resolved_opts(zb_context *ctx, const zb_network *net, int prec, const zb_opts *o)
+{
+    zb_opts r{};
+    if (o) r = *o;
+    r.precision = prec;
+    r.lu = lu_for(ctx, net, prec, o);
+    return r;
+}
+
 int zbh::lanes_for(zb_context *ctx, const zb_network *net, int prec, const zb_opts *o)
 {
     if (o && o->mapping != ZB_MAP_AUTO) return o->mapping;
+    const bool auto_mfma = o && o->lu == ZB_LU_AUTO && lu_for(ctx, net, prec, o) == ZB_LU_MFMA;
     std::lock_guard<std::mutex> lk(ctx->mu);
     for (auto &t : ctx->tuned)
-        if (t.nv == net->dn.nv && t.nr == net->dn.nr && t.prec == prec) return t.lanes;
+        if (t.nv == net->dn.nv && t.nr == net->dn.nr && t.prec == prec)
+            return auto_mfma ? t.auto_lanes : t.lanes;
     // The per-zone LDS area holds the reaction columns (5 doubles a reaction) once per zone of
     // the wave, so a small network with many reactions needs wider groups: widen until two
     // waves fit a CU.
@@ -328,7 +357,7 @@ static bool valid_ptr(const void *p, int device)
 
 zb_err zbh::check_lu(const zb_opts *o, int prec)
 {
-    if (!o || o->lu == ZB_LU_VALU) return ZB_OK;
+    if (!o || o->lu == ZB_LU_VALU || o->lu == ZB_LU_AUTO) return ZB_OK;
     if (o->lu != ZB_LU_MFMA) return fail(ZB_EINVAL, "lu %d", o->lu);
     if (prec != ZB_MIXED) return fail(ZB_EINVAL, "the matrix-core LU is FP32: use ZB_MIXED");
     if (o->integrator == ZB_RKC) return fail(ZB_EINVAL, "the RKC integrator has no LU");
@@ -522,7 +551,6 @@ static zb_err plan_groups(zb_context *ctx, const zb_segment *segs, int n, const 
     }
     if (opts && opts->fp64_fallback != 0 && opts->fp64_fallback != 1)
         return fail(ZB_EINVAL, "fp64_fallback %d", opts->fp64_fallback);
-    const int jac = method_of(opts);
     for (int i = 0; i < n; ++i) {
         zb_err e = check_segment(ctx, segs[i]);
         if (e != ZB_OK) return e;
@@ -530,6 +558,8 @@ static zb_err plan_groups(zb_context *ctx, const zb_segment *segs, int n, const 
     out.clear();
     for (int i = 0; i < n; ++i) {
         if (segs[i].zones == 0) continue;
+        const zb_opts so = resolved_opts(ctx, segs[i].net, prec, opts);
+        const int jac = method_of(&so);
         int lanes = force_lanes ? force_lanes : lanes_for(ctx, segs[i].net, prec, opts);
         const KernelInfo *k = kernel_for(segs[i].net->dn.nv, lanes, prec == ZB_MIXED, jac);
         if (!k)
@@ -831,31 +861,62 @@ extern "C" zb_err zb_graph_destroy(zb_graph *G)
 
 // ----------------------------------------------------------------- autotune
 
-extern "C" zb_err zb_autotune(zb_context *ctx, const zb_network *net, const double *sample_state,
-                              int64_t zones, double dt, double rtol, double atol, int32_t precision,
-                              int32_t *best_lanes, float *times_ms)
+namespace {
+struct TuneRun {
+    zb_tune_candidate c;
+    int li;   // log2 of the lanes
+};
+}  // namespace
+
+// Times the candidates on a copy of the sample: every lanes-per-zone mapping with the vector
+// LU, then (with_mfma) the matrix-core LU where a kernel of it exists for the network.  Each
+// is compared with the first candidate that ran; best_valu / best_all index the fastest
+// qualifying vector-LU candidate and the fastest qualifying one (-1: none).
+static zb_err tune_impl(zb_context *ctx, const zb_network *net, const double *sample_state,
+                        int64_t zones, double dt, double rtol, double atol, int32_t precision,
+                        bool with_mfma, std::vector<TuneRun> &runs, int &best_valu, int &best_all)
 {
     if (!ctx || !net || !sample_state || zones <= 0) return fail(ZB_EINVAL, "bad argument");
+    if (precision != ZB_FP64 && precision != ZB_MIXED) return fail(ZB_EINVAL, "precision %d", precision);
+    {
+        const zb_segment probe = {net, (double *)sample_state, zones, dt, rtol, atol, nullptr, nullptr, nullptr};
+        const zb_err e = check_segment(ctx, probe);
+        if (e != ZB_OK) return e;
+    }
     DeviceGuard g(ctx->device);
     const int row = net->dn.ns + 1;
     const size_t bytes = sizeof(double) * row * (size_t)zones;
+    // the candidates: (lanes, LU)
+    std::vector<std::pair<int, int>> cand;
+    for (int lanes = 1; lanes <= 64; lanes *= 2) cand.push_back({lanes, ZB_LU_VALU});
+    if (with_mfma && precision == ZB_MIXED && net->dn.nv > 32) {
+        const KernelInfo *kb = find_kernel(net->dn.nv, 64, 1, METHOD_BDF_BLU);
+        if (kb) cand.push_back({64, ZB_LU_MFMA});
+    }
     double *work = nullptr;
     int32_t *st = nullptr;
     HIP_TRY(hipMalloc((void **)&work, bytes));
-    HIP_TRY(hipMalloc((void **)&st, sizeof(int32_t) * zones));
+    if (hipMalloc((void **)&st, sizeof(int32_t) * zones) != hipSuccess) {
+        (void)hipFree(work);
+        return fail(ZB_ENOMEM, "autotune scratch");
+    }
     std::vector<double> ref(row * (size_t)zones), cur(row * (size_t)zones);
     std::vector<int32_t> ref_st(zones), cur_st(zones);
-    int best = 0;
-    float best_ms = 0.f;
     bool have_ref = false;
-    zb_opts o{};
-    o.precision = precision;
     zb_err res = ZB_OK;
-    for (int li = 0, lanes = 1; lanes <= 64; ++li, lanes *= 2) {
-        if (times_ms) times_ms[li] = -1.f;
-        const KernelInfo *kk = find_kernel(net->dn.nv, lanes, precision == ZB_MIXED, 0);
-        if (!kk) continue;
-        if (launch_lds(kk, net->dn.nr) > 160 * 1024) continue;   // this mapping cannot launch
+    best_valu = best_all = -1;
+    runs.clear();
+    for (auto [lanes, lu] : cand) {
+        TuneRun R{{lanes, lu, -1.f, 0}, __builtin_ctz((unsigned)lanes)};
+        const KernelInfo *kk = lu == ZB_LU_MFMA ? find_kernel(net->dn.nv, lanes, 1, METHOD_BDF_BLU)
+                                                : find_kernel(net->dn.nv, lanes, precision == ZB_MIXED, 0);
+        if (!kk || launch_lds(kk, net->dn.nr) > 160 * 1024) {   // this candidate cannot launch
+            runs.push_back(R);
+            continue;
+        }
+        zb_opts o{};
+        o.precision = precision;
+        o.lu = lu;
         zb_segment s = {net, work, zones, dt, rtol, atol, nullptr, st, nullptr};
         float ms = 0.f;
         for (int rep = 0; rep < 2; ++rep) {   // the first launch also loads the code object
@@ -869,11 +930,11 @@ extern "C" zb_err zb_autotune(zb_context *ctx, const zb_network *net, const doub
             res = ZB_EDEVICE;
             break;
         }
-        // Every mapping runs the same integrator; only the order of the group
-        // reductions differs, so results agree to rounding except on the rare
-        // ill-conditioned zone.  A mapping qualifies when every zone ends with
-        // the status of the first mapping tried and at least 99% of the zones
-        // agree with it to a gated relative 1e-6.
+        // Every candidate runs the same integrator; the mappings differ only in the order of
+        // the group reductions and the LUs in the rounding of the factorisation, so results
+        // agree to rounding except on the rare ill-conditioned zone.  A candidate qualifies
+        // when every zone ends with the status of the first candidate that ran and at least
+        // 99% of the zones agree with it to a gated relative 1e-6.
         bool ok = true;
         if (!have_ref) {
             ref.swap(cur);
@@ -893,24 +954,64 @@ extern "C" zb_err zb_autotune(zb_context *ctx, const zb_network *net, const doub
             }
             if (ok && agree * 100 < zones * 99) ok = false;
         }
-        if (times_ms) times_ms[li] = ms;
-        if (ok && (best == 0 || ms < best_ms)) {
-            best = lanes;
-            best_ms = ms;
-        }
+        R.c.ms = ms;
+        R.c.qualified = ok ? 1 : 0;
+        runs.push_back(R);
+        const int idx = (int)runs.size() - 1;
+        if (ok && (best_all < 0 || ms < runs[best_all].c.ms)) best_all = idx;
+        if (ok && lu == ZB_LU_VALU && (best_valu < 0 || ms < runs[best_valu].c.ms)) best_valu = idx;
     }
     (void)hipFree(work);
     (void)hipFree(st);
     if (res != ZB_OK) return res;
-    if (!best) return fail(ZB_EUNSUPPORTED, "no mapping ran");
+    if (best_all < 0 || best_valu < 0) return fail(ZB_EUNSUPPORTED, "no mapping ran");
     {
         std::lock_guard<std::mutex> lk(ctx->mu);
+        const zb_context::Tuned t{net->dn.nv, net->dn.nr, precision, runs[best_valu].c.lanes,
+                                  runs[best_all].c.lanes, runs[best_all].c.lu};
         bool found = false;
-        for (auto &t : ctx->tuned)
-            if (t.nv == net->dn.nv && t.nr == net->dn.nr && t.prec == precision) { t.lanes = best; found = true; }
-        if (!found) ctx->tuned.push_back({net->dn.nv, net->dn.nr, precision, best});
+        for (auto &x : ctx->tuned)
+            if (x.nv == t.nv && x.nr == t.nr && x.prec == t.prec) {
+                x = t;
+                found = true;
+            }
+        if (!found) ctx->tuned.push_back(t);
     }
-    if (best_lanes) *best_lanes = best;
+    return ZB_OK;
+}
+
+extern "C" zb_err zb_autotune(zb_context *ctx, const zb_network *net, const double *sample_state,
+                              int64_t zones, double dt, double rtol, double atol, int32_t precision,
+                              int32_t *best_lanes, float *times_ms)
+{
+    std::vector<TuneRun> runs;
+    int bv = -1, ba = -1;
+    const zb_err e = tune_impl(ctx, net, sample_state, zones, dt, rtol, atol, precision, false,
+                               runs, bv, ba);
+    if (times_ms) {
+        for (int i = 0; i < 7; ++i) times_ms[i] = -1.f;
+        for (auto &r : runs) times_ms[r.li] = r.c.ms;
+    }
+    if (e != ZB_OK) return e;
+    if (best_lanes) *best_lanes = runs[bv].c.lanes;
+    return ZB_OK;
+}
+
+extern "C" zb_err zb_autotune_candidates(zb_context *ctx, const zb_network *net,
+                                         const double *sample_state, int64_t zones, double dt,
+                                         double rtol, double atol, int32_t precision,
+                                         zb_tune_candidate *out, int32_t max_out, int32_t *n_out,
+                                         int32_t *best)
+{
+    if (max_out < 0 || (max_out > 0 && !out)) return fail(ZB_EINVAL, "bad candidate buffer");
+    std::vector<TuneRun> runs;
+    int bv = -1, ba = -1;
+    const zb_err e = tune_impl(ctx, net, sample_state, zones, dt, rtol, atol, precision, true,
+                               runs, bv, ba);
+    for (int i = 0; i < (int)runs.size() && i < max_out; ++i) out[i] = runs[i].c;
+    if (n_out) *n_out = (int32_t)runs.size();
+    if (e != ZB_OK) return e;
+    if (best) *best = ba;
     return ZB_OK;
 }
 

@@ -67,7 +67,7 @@ constexpr int FB_CAPTURE_SLOTS = 4;
 const zb::KernelInfo *find_kernel(int nv, int lanes, int mixed, int jac);
 const zb::KernelInfo *kernel_for(int nv, int lanes, int mixed, int method);
 
-// Kernel method (METHOD_*) of validated options.
+// Kernel method (METHOD_*) of validated options whose lu is resolved (not ZB_LU_AUTO).
 inline int method_of(const zb_opts *o)
 {
     if (!o) return zb::METHOD_BDF;
@@ -79,6 +79,10 @@ inline int method_of(const zb_opts *o)
 // zb_opts.lu against the rest of the options (precision prec).
 zb_err check_lu(const zb_opts *o, int prec);
 int lanes_for(zb_context *ctx, const zb_network *net, int prec, const zb_opts *o);
+// zb_opts.lu for one network: ZB_LU_AUTO resolved from the context's tuning.
+int lu_for(zb_context *ctx, const zb_network *net, int prec, const zb_opts *o);
+// The options of one segment: lu resolved (lu_for).
+zb_opts resolved_opts(zb_context *ctx, const zb_network *net, int prec, const zb_opts *o);
 zb_err check_segment(zb_context *ctx, const zb_segment &s);
 // Validates the segments and launches them (one persistent launch per kernel
 // class) on `stream`.  ws = nullptr takes a rotating slot of the context.
@@ -106,8 +110,9 @@ struct zb_context {
     // this device's copy of the static scratch array (zb_burn_batch_noalloc)
     unsigned long long *static_scratch = nullptr;
     std::mutex mu;
-    // autotuned lanes per zone, keyed by (nv, nr, precision)
-    struct Tuned { int nv, nr, prec, lanes; };
+    // autotuned choices keyed by (nv, nr, precision): lanes per zone with the vector LU, and
+    // the fastest (lanes, LU) pair overall, for ZB_LU_AUTO
+    struct Tuned { int nv, nr, prec, lanes, auto_lanes, auto_lu; };
     std::vector<Tuned> tuned;
     // side streams for calls that launch several kernel classes (default priority)
     std::mutex fork_mu;

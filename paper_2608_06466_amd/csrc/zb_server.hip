@@ -351,8 +351,9 @@ extern "C" zb_err zb_server_submit(zb_server *S, const zb_network *net, const do
         return fail(ZB_EINVAL, "dt, rtol and atol must be finite and > 0");
     const int row = net->dn.ns + 1;
     const int lanes = lanes_for(S->ctx, net, S->opts.precision, &S->opts);
+    const zb_opts ro = resolved_opts(S->ctx, net, S->opts.precision, &S->opts);
     const KernelInfo *k = kernel_for(net->dn.nv, lanes, S->opts.precision == ZB_MIXED,
-                                     method_of(&S->opts));
+                                     method_of(&ro));
     if (!k) return fail(ZB_EUNSUPPORTED, "no kernel for nv=%d with %d lanes", net->dn.nv, lanes);
     auto al = arena_round;
     size_t bytes = al(sizeof(double) * row * (size_t)zones) + al(sizeof(int32_t) * (size_t)zones) +

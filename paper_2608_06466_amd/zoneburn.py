@@ -57,6 +57,11 @@ class _ServerOpts(C.Structure):
                 ("max_pending", C.c_int32), ("reserved", C.c_int32), ("burn", _Opts)]
 
 
+class _TuneCand(C.Structure):
+    _fields_ = [("lanes", C.c_int32), ("lu", C.c_int32), ("ms", C.c_float),
+                ("qualified", C.c_int32)]
+
+
 class _ReqInfo(C.Structure):
     _fields_ = [("zones", C.c_int64), ("zones_ok", C.c_int64), ("queue_s", C.c_double),
                 ("first_launch_s", C.c_double), ("latency_s", C.c_double)]
@@ -91,6 +96,8 @@ def lib():
             "zb_burn_batch_noalloc": [p, C.POINTER(_Segment), i32, C.POINTER(_Opts), p],
             "zb_get_mapping": [p, p, i32, C.POINTER(i32)],
             "zb_autotune": [p, p, p, i64, d, d, d, i32, C.POINTER(i32), C.POINTER(C.c_float)],
+            "zb_autotune_candidates": [p, p, p, i64, d, d, d, i32, C.POINTER(_TuneCand), i32,
+                                       C.POINTER(i32), C.POINTER(i32)],
             "zb_graph_create": [p, C.POINTER(_Segment), i32, C.POINTER(_Opts), C.POINTER(p)],
             "zb_graph_launch": [p, p],
             "zb_graph_destroy": [p],
@@ -192,14 +199,15 @@ def _opts(precision, lanes, max_steps, retry=None, jac_policy=0, integrator=0, l
     zones, jac "analytic" (default) or "fd" (finite-difference Jacobian in the retry).
     jac_policy: 0 Jacobian and LU every step attempt, 1 VODE-style reuse.
     integrator: "bdf" (0), "rkc" (1) or "bdf_variable" (2, VODE's variable-coefficient form).
-    lu: "valu" (0) or "mfma" (1, the blocked FP32 LU on the matrix cores; 48-row kernels).
+    lu: "valu" (0), "mfma" (1, the blocked FP32 LU on the matrix cores; 48-row kernels) or
+    "auto" (2, the pair of LU and lanes per zone autotune_candidates chose for the network).
     fp64_fallback: mixed precision only; zones that fail are burned again in FP64."""
     prec = {"fp64": FP64, "mixed": MIXED, FP64: FP64, MIXED: MIXED}[precision]
     jp = {"every_step": 0, "reuse": 1, 0: 0, 1: 1}[jac_policy]
     it = {"bdf": 0, "rkc": 1, "bdf_variable": 2, 0: 0, 1: 1, 2: 2}[integrator]
-    lv = {"valu": 0, "mfma": 1, 0: 0, 1: 1}.get(lu)
+    lv = {"valu": 0, "mfma": 1, "auto": 2, 0: 0, 1: 1, 2: 2}.get(lu)
     if lv is None:
-        raise ValueError("lu must be 'valu' or 'mfma'")
+        raise ValueError("lu must be 'valu', 'mfma' or 'auto'")
     if retry is None:
         return _Opts(int(max_steps or 0), prec, int(lanes or 0), 0, 0.0, 0.0, 0, jp, it, 0, lv,
                      int(bool(fp64_fallback)))
@@ -438,3 +446,19 @@ def autotune(ctx, net, sample_state, dt, rtol, atol, precision="fp64"):
                              float(rtol), float(atol), _opts(precision, 0, 0).precision,
                              C.byref(best), times), "zb_autotune")
     return int(best.value), list(times)
+
+
+def autotune_candidates(ctx, net, sample_state, dt, rtol, atol, precision="mixed"):
+    """Times every (lanes per zone, LU) candidate on sample_state (zb_autotune_candidates);
+    returns (candidates, best index), each candidate a dict with lanes, lu ('valu'/'mfma'),
+    ms and qualified.  The chosen pair then serves calls with lu='auto'."""
+    _check_state(net, sample_state)
+    buf = (_TuneCand * 16)()
+    n, best = C.c_int32(0), C.c_int32(-1)
+    _check(lib().zb_autotune_candidates(ctx.h, net.h, _ptr(sample_state), sample_state.shape[0],
+                                        float(dt), float(rtol), float(atol),
+                                        _opts(precision, 0, 0).precision, buf, 16, C.byref(n),
+                                        C.byref(best)), "zb_autotune_candidates")
+    out = [{"lanes": int(c.lanes), "lu": ("valu", "mfma")[c.lu], "ms": float(c.ms),
+            "qualified": bool(c.qualified)} for c in buf[:min(16, n.value)]]
+    return out, int(best.value)

@@ -63,7 +63,7 @@ def test_struct_layouts_match_the_binding(tmp_path):
         pytest.skip("no C compiler")
     structs = {"zb_server_opts": zb._ServerOpts, "zb_request_info": zb._ReqInfo,
                "zb_server_totals": zb._Totals, "zb_segment": zb._Segment, "zb_opts": zb._Opts,
-               "zb_network_desc": zb._Desc}
+               "zb_network_desc": zb._Desc, "zb_tune_candidate": zb._TuneCand}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "zoneburn.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

@@ -452,6 +452,54 @@ def test_variable_coefficient_bdf_parity(zbm, which, jac_policy, precision):
     net.close()
 
 
+def test_autotune_candidates_cover_the_lu_and_serve_lu_auto(zbm):
+    """zb_autotune_candidates times every lanes-per-zone mapping with the vector LU and, for
+    the 48-variable network in mixed precision, the matrix-core LU on 64 lanes.  The fastest
+    qualifying pair then serves lu='auto' calls bit for bit as the same explicit options do;
+    lu='valu' calls with the automatic mapping take the fastest vector-LU mapping; lu='auto'
+    falls back to the vector LU in FP64 and with the reused Jacobian.  A context of its own,
+    so that the tuning reaches no other test."""
+    zb, _ = zbm
+    ctx = zb.Context(0)
+    ns, R, seed = W.BATCHED_NETS[2]
+    net_d = W.random_network(ns, R, seed)
+    net = zb.Network(ctx, net_d)
+    st = torch.tensor(W.random_zones(net_d, 1024, seed=77, T_range=W.BATCHED_T_RANGE,
+                                     T_dist="loguniform"), device="cuda:0")
+    before = st.clone()
+    cands, best = zb.autotune_candidates(ctx, net, st, 1.0, 1e-8, 1e-12, "mixed")
+    print("candidates:", [(c["lanes"], c["lu"], round(c["ms"], 2), c["qualified"]) for c in cands],
+          "best", best, flush=True)
+    assert torch.equal(st, before)
+    pairs = [(c["lanes"], c["lu"]) for c in cands]
+    assert pairs == [(1 << i, "valu") for i in range(7)] + [(64, "mfma")]
+    ran = [i for i, c in enumerate(cands) if c["ms"] > 0]
+    assert 6 in ran and 7 in ran
+    q = [i for i in ran if cands[i]["qualified"]]
+    assert 7 in q, "the matrix-core LU agrees with the vector LU"
+    assert best in q and cands[best]["ms"] == min(cands[i]["ms"] for i in q)
+    bv = min((i for i in q if cands[i]["lu"] == "valu"), key=lambda i: cands[i]["ms"])
+    assert zb.get_mapping(ctx, net, "mixed") == cands[bv]["lanes"]
+    sub = W.random_zones(net_d, 128, seed=78, T_range=W.BATCHED_T_RANGE, T_dist="loguniform")
+    auto = run_gpu(zb, ctx, net_d, sub, 1.0, 1e-8, 1e-12, precision="mixed", lu="auto", net=net)
+    expl = run_gpu(zb, ctx, net_d, sub, 1.0, 1e-8, 1e-12, precision="mixed",
+                   lanes=cands[best]["lanes"], lu=cands[best]["lu"], net=net)
+    for a, b in zip(auto, expl):
+        assert np.array_equal(a, b)
+    valu = run_gpu(zb, ctx, net_d, sub, 1.0, 1e-8, 1e-12, precision="mixed", lu="valu", net=net)
+    vexp = run_gpu(zb, ctx, net_d, sub, 1.0, 1e-8, 1e-12, precision="mixed",
+                   lanes=cands[bv]["lanes"], lu="valu", net=net)
+    for a, b in zip(valu, vexp):
+        assert np.array_equal(a, b)
+    for kw in (dict(precision="fp64"), dict(precision="mixed", jac_policy=1)):
+        a = run_gpu(zb, ctx, net_d, sub[:32], 1.0, 1e-8, 1e-12, lu="auto", net=net, **kw)
+        b = run_gpu(zb, ctx, net_d, sub[:32], 1.0, 1e-8, 1e-12, lu="valu", net=net, **kw)
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y), kw
+    net.close()
+    ctx.close()
+
+
 @pytest.mark.parametrize("lanes", [1, 4])
 def test_variable_coefficient_bdf_robertson(zbm, lanes):
     zb, ctx = zbm
