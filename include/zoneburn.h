@@ -306,9 +306,14 @@ zb_err zb_get_mapping(zb_context *ctx, const zb_network *net, int32_t precision,
    and use the fastest qualifying one for (network size, reactions, precision) on this context
    from now on, with the vector LU (ZB_LU_AUTO then resolves to ZB_LU_VALU as well).  A mapping qualifies when every sample zone ends with the status the first
    mapping gave it and at least 99% of the zones agree with that mapping to a gated relative
-   1e-6 (the mappings differ only in the order of reductions).  times_ms (HOST, optional)
-   receives one entry per lane count 1,2,4,...,64 (negative when unsupported).  Allocates
-   device scratch for one copy of the sample; synchronous. */
+   1e-6 (the mappings differ only in the order of reductions).  The sample is burned once
+   first for its step counts; each mapping is then timed on the sample ordered longest zone
+   first and repeated (copies of a zone side by side, at most 16) until it fills the GPU's
+   resident zones of that mapping 8 times over, so that the times follow the steady
+   throughput rather than the ramp-down at the end.  times_ms (HOST, optional) receives one
+   entry per lane count 1,2,4,...,64, per copy of the sample (negative when unsupported).
+   Allocates device scratch for up to 32 copies of the sample and host memory for 17;
+   synchronous. */
 zb_err zb_autotune(zb_context *ctx, const zb_network *net, const double *sample_state,
                    int64_t zones, double dt, double rtol, double atol, int32_t precision,
                    int32_t *best_lanes, float *times_ms);
@@ -317,7 +322,7 @@ zb_err zb_autotune(zb_context *ctx, const zb_network *net, const double *sample_
 typedef struct {
     int32_t lanes;       /* lanes per zone */
     int32_t lu;          /* ZB_LU_VALU or ZB_LU_MFMA */
-    float ms;            /* burn time of the sample (the second of two runs) */
+    float ms;            /* burn time per copy of the sample (see zb_autotune); < 0: not run */
     int32_t qualified;   /* 1: statuses equal to the first candidate's, >= 99 % of the zones
                             within a gated relative 1e-6 of it */
 } zb_tune_candidate;
@@ -329,13 +334,27 @@ typedef struct {
    candidate then serves launches with zb_opts.lu = ZB_LU_AUTO and mapping ZB_MAP_AUTO; the
    fastest qualifying vector-LU one serves launches with ZB_LU_VALU and ZB_MAP_AUTO (what
    zb_autotune records).  out (HOST, max_out entries, optional) receives the candidates in the
-   order tried, *n_out their number and *best (optional) the index of the chosen one.
-   ZB_EUNSUPPORTED when no candidate ran.  Allocates device scratch for one copy of the
-   sample; synchronous. */
+   order tried, *n_out their number and *best (optional) the index of the chosen one.  Timed
+   as in zb_autotune (ms per copy of the sample).  ZB_EUNSUPPORTED when no candidate ran.
+   Allocates as zb_autotune does; synchronous. */
 zb_err zb_autotune_candidates(zb_context *ctx, const zb_network *net, const double *sample_state,
                               int64_t zones, double dt, double rtol, double atol,
                               int32_t precision, zb_tune_candidate *out, int32_t max_out,
                               int32_t *n_out, int32_t *best);
+
+/* The context's autotuned choices (zb_autotune, zb_autotune_candidates) as a JSON file at
+   `path` (HOST string): one entry per (network size, reactions, precision) with the lanes per
+   zone of the vector LU and the (lanes, LU) pair of ZB_LU_AUTO, keyed by the device's
+   architecture name and the HIP runtime version.  The file is written beside `path` and
+   renamed over it.  ZB_EINVAL when it cannot be written. */
+zb_err zb_tune_save(zb_context *ctx, const char *path);
+/* Adds the choices of a file written by zb_tune_save to this context's table (replacing
+   entries of the same key); *loaded (optional) receives the number applied.  A file from
+   another architecture or HIP runtime version applies nothing (*loaded = 0, ZB_OK), and
+   entries naming a kernel this library does not hold are skipped.  ZB_EINVAL for a missing,
+   unreadable, malformed or over-1-MiB file, or values out of range (the table is then left
+   as it was). */
+zb_err zb_tune_load(zb_context *ctx, const char *path, int32_t *loaded);
 
 /* Human-readable name of an error code and the last error message of this thread. */
 const char *zb_strerror(zb_err err);

@@ -74,6 +74,7 @@ extern "C" zb_err zb_context_create(int device, zb_context **out)
     if (!c) return fail(ZB_ENOMEM, "host allocation failed");
     c->device = device;
     c->cus = prop.multiProcessorCount;
+    c->arch = prop.gcnArchName;
     const size_t nq = 1 + (size_t)(QUEUE_SLOTS + QUEUE_CAPTURE_SLOTS) * MAXSEG;
     if (hipMalloc((void **)&c->ws, sizeof(unsigned long long) * nq) != hipSuccess) {
         delete c;
@@ -893,60 +894,140 @@ static zb_err tune_impl(zb_context *ctx, const zb_network *net, const double *sa
         const KernelInfo *kb = find_kernel(net->dn.nv, 64, 1, METHOD_BDF_BLU);
         if (kb) cand.push_back({64, ZB_LU_MFMA});
     }
-    double *work = nullptr;
+    // Each candidate's kernel, and how many copies of the sample it is timed on: the sample,
+    // ordered longest zone first, fills the GPU's resident zones at least 8 times over
+    // (copies of a zone side by side; at most 16 copies).  A sample that fills them only a
+    // few times is timed mostly in its ramp-down, with few waves left to hide latencies: on
+    // 8192 zones of the 48-variable network (4 times the resident 2048) the matrix-core LU
+    // ran 5 % slower than the vector LU, from 16384 zones on 2.5 % faster, as on the whole
+    // 262144-zone segment (1.7 %).
+    struct Cand {
+        int lanes, lu, reps;
+        const KernelInfo *k;
+    };
+    std::vector<Cand> cs;
+    int rmax = 1;
+    for (auto [lanes, lu] : cand) {
+        const KernelInfo *kk = lu == ZB_LU_MFMA ? find_kernel(net->dn.nv, lanes, 1, METHOD_BDF_BLU)
+                                                : find_kernel(net->dn.nv, lanes, precision == ZB_MIXED, 0);
+        int reps = 0;
+        if (kk && launch_lds(kk, net->dn.nr) <= 160 * 1024) {
+            const int64_t resident = (int64_t)blocks_per_cu(kk, net->dn.nr) * ctx->cus * (64 / lanes);
+            reps = (int)std::min<int64_t>(16, std::max<int64_t>(1, (8 * resident + zones - 1) / zones));
+            if (resident <= 0) kk = nullptr;
+        } else {
+            kk = nullptr;
+        }
+        cs.push_back({lanes, lu, kk ? reps : 0, kk});
+        if (kk) rmax = std::max(rmax, reps);
+    }
+    const size_t rep_zones = (size_t)zones * rmax;
+    double *work = nullptr, *ordered = nullptr;
     int32_t *st = nullptr;
-    HIP_TRY(hipMalloc((void **)&work, bytes));
-    if (hipMalloc((void **)&st, sizeof(int32_t) * zones) != hipSuccess) {
+    zb_zone_stats *zs = nullptr;
+    HIP_TRY(hipMalloc((void **)&work, bytes * rmax));
+    if (hipMalloc((void **)&ordered, bytes * rmax) != hipSuccess ||
+        hipMalloc((void **)&st, sizeof(int32_t) * rep_zones) != hipSuccess ||
+        hipMalloc((void **)&zs, sizeof(zb_zone_stats) * zones) != hipSuccess) {
         (void)hipFree(work);
+        (void)hipFree(ordered);
+        (void)hipFree(st);
         return fail(ZB_ENOMEM, "autotune scratch");
     }
-    std::vector<double> ref(row * (size_t)zones), cur(row * (size_t)zones);
-    std::vector<int32_t> ref_st(zones), cur_st(zones);
+    auto release = [&]() {
+        (void)hipFree(work);
+        (void)hipFree(ordered);
+        (void)hipFree(st);
+        (void)hipFree(zs);
+    };
+    std::vector<double> ref(row * (size_t)zones), cur(row * rep_zones), lpt(row * (size_t)zones);
+    std::vector<int32_t> ref_st(zones), cur_st(rep_zones);
+    // Zones are handed out in queue order, so the time of a sample in its given order is
+    // mostly that of whichever long zones happen to start last: on 8192 zones of the
+    // 48-variable network it scatters by about 2 % between runs, more than the candidates
+    // differ.  The sample is therefore burned once first, for its step counts, and the
+    // candidates are timed on it longest first: the time then follows the throughput.
+    {
+        zb_opts o{};
+        o.precision = precision;
+        zb_segment s = {net, work, zones, dt, rtol, atol, nullptr, st, zs};
+        std::vector<zb_zone_stats> hs(zones);
+        std::vector<int64_t> order(zones);
+        zb_err e = ZB_OK;
+        if (hipMemcpy(work, sample_state, bytes, hipMemcpyDeviceToDevice) != hipSuccess) e = ZB_EDEVICE;
+        if (e == ZB_OK) e = burn_impl(ctx, &s, 1, &o, nullptr, 0, nullptr);
+        if (e == ZB_OK && (hipDeviceSynchronize() != hipSuccess ||
+                           hipMemcpy(hs.data(), zs, sizeof(zb_zone_stats) * zones, hipMemcpyDeviceToHost) != hipSuccess ||
+                           hipMemcpy(ref.data(), sample_state, bytes, hipMemcpyDeviceToHost) != hipSuccess))
+            e = ZB_EDEVICE;
+        if (e != ZB_OK) {
+            release();
+            return e;
+        }
+        for (int64_t z = 0; z < zones; ++z) order[z] = z;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int64_t a, int64_t b) { return hs[a].nst > hs[b].nst; });
+        for (int64_t z = 0; z < zones; ++z)
+            memcpy(&lpt[z * row], &ref[order[z] * row], sizeof(double) * row);
+    }
     bool have_ref = false;
     zb_err res = ZB_OK;
     best_valu = best_all = -1;
     runs.clear();
-    for (auto [lanes, lu] : cand) {
+    for (const Cand &C : cs) {
+        const int lanes = C.lanes, lu = C.lu;
         TuneRun R{{lanes, lu, -1.f, 0}, __builtin_ctz((unsigned)lanes)};
-        const KernelInfo *kk = lu == ZB_LU_MFMA ? find_kernel(net->dn.nv, lanes, 1, METHOD_BDF_BLU)
-                                                : find_kernel(net->dn.nv, lanes, precision == ZB_MIXED, 0);
-        if (!kk || launch_lds(kk, net->dn.nr) > 160 * 1024) {   // this candidate cannot launch
+        if (!C.k) {   // this candidate cannot launch
             runs.push_back(R);
             continue;
+        }
+        const int r = C.reps;
+        const int64_t nz = zones * (int64_t)r;
+        const size_t nb = bytes * r;
+        for (int64_t z = 0; z < zones; ++z)
+            for (int c = 0; c < r; ++c)
+                memcpy(&cur[(z * r + c) * row], &lpt[z * row], sizeof(double) * row);
+        if (hipMemcpy(ordered, cur.data(), nb, hipMemcpyHostToDevice) != hipSuccess) {
+            res = fail(ZB_EDEVICE, "autotune sample upload");
+            break;
         }
         zb_opts o{};
         o.precision = precision;
         o.lu = lu;
-        zb_segment s = {net, work, zones, dt, rtol, atol, nullptr, st, nullptr};
         float ms = 0.f;
-        for (int rep = 0; rep < 2; ++rep) {   // the first launch also loads the code object
-            if (hipMemcpy(work, sample_state, bytes, hipMemcpyDeviceToDevice) != hipSuccess) { res = ZB_EDEVICE; break; }
+        // the first launch, over one copy, also loads the code object; the second is timed
+        for (int rep = 0; rep < 2; ++rep) {
+            zb_segment s = {net, work, rep ? nz : zones, dt, rtol, atol, nullptr, st, nullptr};
+            if (hipMemcpy(work, ordered, rep ? nb : bytes, hipMemcpyDeviceToDevice) != hipSuccess) { res = ZB_EDEVICE; break; }
             zb_err e = burn_impl(ctx, &s, 1, &o, nullptr, lanes, &ms);
             if (e != ZB_OK) { res = e; break; }
         }
         if (res != ZB_OK) break;
-        if (hipMemcpy(cur.data(), work, bytes, hipMemcpyDeviceToHost) != hipSuccess ||
-            hipMemcpy(cur_st.data(), st, sizeof(int32_t) * zones, hipMemcpyDeviceToHost) != hipSuccess) {
+        if (hipMemcpy(cur.data(), work, nb, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(cur_st.data(), st, sizeof(int32_t) * nz, hipMemcpyDeviceToHost) != hipSuccess) {
             res = ZB_EDEVICE;
             break;
         }
         // Every candidate runs the same integrator; the mappings differ only in the order of
         // the group reductions and the LUs in the rounding of the factorisation, so results
         // agree to rounding except on the rare ill-conditioned zone.  A candidate qualifies
-        // when every zone ends with the status of the first candidate that ran and at least
-        // 99% of the zones agree with it to a gated relative 1e-6.
+        // when every zone (the first copy of each) ends with the status of the first
+        // candidate that ran and at least 99% of the zones agree with it to a gated relative
+        // 1e-6.
         bool ok = true;
         if (!have_ref) {
-            ref.swap(cur);
-            ref_st.swap(cur_st);
+            for (int64_t z = 0; z < zones; ++z) {
+                memcpy(&ref[z * row], &cur[z * r * row], sizeof(double) * row);
+                ref_st[z] = cur_st[z * r];
+            }
             have_ref = true;
         } else {
             int64_t agree = 0;
             for (int64_t z = 0; z < zones && ok; ++z) {
-                if (cur_st[z] != ref_st[z]) ok = false;
+                if (cur_st[z * r] != ref_st[z]) ok = false;
                 bool zok = true;
                 for (int i = 0; i < row; ++i) {
-                    double a = ref[z * row + i], b = cur[z * row + i];
+                    double a = ref[z * row + i], b = cur[z * r * row + i];
                     double den = fmax(fabs(a), atol / rtol);
                     if (!(fabs(a - b) <= 1e-6 * den)) zok = false;
                 }
@@ -954,6 +1035,7 @@ static zb_err tune_impl(zb_context *ctx, const zb_network *net, const double *sa
             }
             if (ok && agree * 100 < zones * 99) ok = false;
         }
+        ms /= (float)r;   // per copy of the sample
         R.c.ms = ms;
         R.c.qualified = ok ? 1 : 0;
         runs.push_back(R);
@@ -961,8 +1043,7 @@ static zb_err tune_impl(zb_context *ctx, const zb_network *net, const double *sa
         if (ok && (best_all < 0 || ms < runs[best_all].c.ms)) best_all = idx;
         if (ok && lu == ZB_LU_VALU && (best_valu < 0 || ms < runs[best_valu].c.ms)) best_valu = idx;
     }
-    (void)hipFree(work);
-    (void)hipFree(st);
+    release();
     if (res != ZB_OK) return res;
     if (best_all < 0 || best_valu < 0) return fail(ZB_EUNSUPPORTED, "no mapping ran");
     {
@@ -1012,6 +1093,85 @@ extern "C" zb_err zb_autotune_candidates(zb_context *ctx, const zb_network *net,
     if (n_out) *n_out = (int32_t)runs.size();
     if (e != ZB_OK) return e;
     if (best) *best = ba;
+    return ZB_OK;
+}
+
+// ------------------------------------------------------------ tuning cache
+
+extern "C" zb_err zb_tune_save(zb_context *ctx, const char *path)
+{
+    if (!ctx || !path) return fail(ZB_EINVAL, "NULL argument");
+    int rt = 0;
+    HIP_TRY(hipRuntimeGetVersion(&rt));
+    std::vector<TuneEntry> es;
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        es = ctx->tuned;
+    }
+    const std::string text = tune_json(ctx->arch, rt, es);
+    // written next to the target and renamed over it, so a reader never sees half a file
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "wb");
+    if (!f) return fail(ZB_EINVAL, "cannot write %s", tmp.c_str());
+    const bool ok = fwrite(text.data(), 1, text.size(), f) == text.size();
+    if (fclose(f) != 0 || !ok) {
+        remove(tmp.c_str());
+        return fail(ZB_EINVAL, "cannot write %s", tmp.c_str());
+    }
+    if (rename(tmp.c_str(), path) != 0) {
+        remove(tmp.c_str());
+        return fail(ZB_EINVAL, "cannot replace %s", path);
+    }
+    return ZB_OK;
+}
+
+extern "C" zb_err zb_tune_load(zb_context *ctx, const char *path, int32_t *loaded)
+{
+    if (!ctx || !path) return fail(ZB_EINVAL, "NULL argument");
+    if (loaded) *loaded = 0;
+    FILE *f = fopen(path, "rb");
+    if (!f) return fail(ZB_EINVAL, "cannot read %s", path);
+    std::string text;
+    char buf[4096];
+    size_t n;
+    while ((n = fread(buf, 1, sizeof buf, f)) > 0) {
+        text.append(buf, n);
+        if (text.size() > (1u << 20)) {
+            fclose(f);
+            return fail(ZB_EINVAL, "%s is larger than 1 MiB", path);
+        }
+    }
+    const bool rd_err = ferror(f) != 0;
+    fclose(f);
+    if (rd_err) return fail(ZB_EINVAL, "cannot read %s", path);
+    std::string arch, err;
+    int rt_file = 0;
+    std::vector<TuneEntry> es;
+    if (!tune_parse(text, NVMAX, RMAX, arch, rt_file, es, err)) return fail(ZB_EINVAL, "%s: %s", path, err.c_str());
+    int rt = 0;
+    HIP_TRY(hipRuntimeGetVersion(&rt));
+    // timings from another GPU or HIP runtime say nothing about this one
+    if (arch != ctx->arch || rt_file != rt) return ZB_OK;
+    int applied = 0;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    for (const TuneEntry &e : es) {
+        // an entry naming a kernel this library does not hold, or one whose LDS does not fit
+        // a CU, is skipped
+        const KernelInfo *kv = find_kernel(e.nv, e.lanes, e.prec == ZB_MIXED, METHOD_BDF);
+        const KernelInfo *ka = e.auto_lu == ZB_LU_MFMA
+                                   ? (e.prec == ZB_MIXED && e.nv > 32 ? find_kernel(e.nv, e.auto_lanes, 1, METHOD_BDF_BLU) : nullptr)
+                                   : find_kernel(e.nv, e.auto_lanes, e.prec == ZB_MIXED, METHOD_BDF);
+        if (!kv || !ka || launch_lds(kv, e.nr) > 160 * 1024 || launch_lds(ka, e.nr) > 160 * 1024) continue;
+        bool found = false;
+        for (auto &x : ctx->tuned)
+            if (x.nv == e.nv && x.nr == e.nr && x.prec == e.prec) {
+                x = e;
+                found = true;
+            }
+        if (!found) ctx->tuned.push_back(e);
+        ++applied;
+    }
+    if (loaded) *loaded = applied;
     return ZB_OK;
 }
 

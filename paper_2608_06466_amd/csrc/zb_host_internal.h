@@ -10,6 +10,7 @@
 
 #include "zb_internal.h"
 #include "zb_slots.h"
+#include "zb_tunecache.h"
 #include "zoneburn.h"
 
 namespace zbh {
@@ -112,8 +113,9 @@ struct zb_context {
     std::mutex mu;
     // autotuned choices keyed by (nv, nr, precision): lanes per zone with the vector LU, and
     // the fastest (lanes, LU) pair overall, for ZB_LU_AUTO
-    struct Tuned { int nv, nr, prec, lanes, auto_lanes, auto_lu; };
+    using Tuned = zbh::TuneEntry;
     std::vector<Tuned> tuned;
+    std::string arch;   // gcnArchName of the device, the key of saved tunings
     // side streams for calls that launch several kernel classes (default priority)
     std::mutex fork_mu;
     std::vector<hipStream_t> side;

@@ -96,6 +96,8 @@ def lib():
             "zb_burn_batch_noalloc": [p, C.POINTER(_Segment), i32, C.POINTER(_Opts), p],
             "zb_get_mapping": [p, p, i32, C.POINTER(i32)],
             "zb_autotune": [p, p, p, i64, d, d, d, i32, C.POINTER(i32), C.POINTER(C.c_float)],
+            "zb_tune_save": [p, C.c_char_p],
+            "zb_tune_load": [p, C.c_char_p, C.POINTER(i32)],
             "zb_autotune_candidates": [p, p, p, i64, d, d, d, i32, C.POINTER(_TuneCand), i32,
                                        C.POINTER(i32), C.POINTER(i32)],
             "zb_graph_create": [p, C.POINTER(_Segment), i32, C.POINTER(_Opts), C.POINTER(p)],
@@ -446,6 +448,19 @@ def autotune(ctx, net, sample_state, dt, rtol, atol, precision="fp64"):
                              float(rtol), float(atol), _opts(precision, 0, 0).precision,
                              C.byref(best), times), "zb_autotune")
     return int(best.value), list(times)
+
+
+def tune_save(ctx, path):
+    """Writes the context's autotuned choices to a JSON file (zb_tune_save)."""
+    _check(lib().zb_tune_save(ctx.h, os.fsencode(path)), "zb_tune_save")
+
+
+def tune_load(ctx, path):
+    """Loads choices saved by tune_save into the context; returns how many applied (0 for a
+    file from another GPU architecture or HIP runtime)."""
+    n = C.c_int32(0)
+    _check(lib().zb_tune_load(ctx.h, os.fsencode(path), C.byref(n)), "zb_tune_load")
+    return int(n.value)
 
 
 def autotune_candidates(ctx, net, sample_state, dt, rtol, atol, precision="mixed"):

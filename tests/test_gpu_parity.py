@@ -500,6 +500,58 @@ def test_autotune_candidates_cover_the_lu_and_serve_lu_auto(zbm):
     ctx.close()
 
 
+def test_tuning_file_carries_the_choices_to_another_context(zbm, tmp_path):
+    """zb_tune_save writes the context's autotuned choices; zb_tune_load applies them in
+    another context (the loaded mapping then serves AUTO launches bit for bit as the explicit
+    one), applies nothing from another architecture, and refuses malformed or missing files."""
+    import json
+    zb, _ = zbm
+    a = zb.Context(0)
+    c = W.nv14(2048)
+    net = zb.Network(a, c["net"])
+    best, _ = zb.autotune(a, net, torch.tensor(c["state"], device="cuda:0"), 1.0, 1e-8, 1e-12,
+                          precision="mixed")
+    path = tmp_path / "tune.json"
+    zb.tune_save(a, path)
+    doc = json.loads(path.read_text())
+    assert doc["format"] == "zoneburn-tune-1" and doc["arch"].startswith("gfx950")
+    assert doc["entries"] == [{"nv": 14, "nr": 30, "precision": 1, "lanes": best,
+                               "auto_lanes": best, "auto_lu": 0}]
+    net.close()
+    a.close()
+    # another mapping than the default, written by hand, so that the load is visible
+    doc["entries"][0]["lanes"] = doc["entries"][0]["auto_lanes"] = 8
+    path.write_text(json.dumps(doc))
+    b = zb.Context(0)
+    netb = zb.Network(b, c["net"])
+    default = zb.get_mapping(b, netb, "mixed")
+    assert default == 16
+    assert zb.tune_load(b, path) == 1
+    assert zb.get_mapping(b, netb, "mixed") == 8
+    assert zb.get_mapping(b, netb, "fp64") == default
+    auto = run_gpu(zb, b, c["net"], c["state"][:64], 1.0, 1e-8, 1e-12, precision="mixed", net=netb)
+    expl = run_gpu(zb, b, c["net"], c["state"][:64], 1.0, 1e-8, 1e-12, precision="mixed", lanes=8,
+                   net=netb)
+    for x, y in zip(auto, expl):
+        assert np.array_equal(x, y)
+    netb.close()
+    b.close()
+    other = dict(doc, arch="gfx000")
+    (tmp_path / "other.json").write_text(json.dumps(other))
+    c2 = zb.Context(0)
+    net2 = zb.Network(c2, c["net"])
+    assert zb.tune_load(c2, tmp_path / "other.json") == 0
+    assert zb.get_mapping(c2, net2, "mixed") == default
+    (tmp_path / "bad.json").write_text(path.read_text()[:-5])
+    for p in (tmp_path / "bad.json", tmp_path / "missing.json"):
+        with pytest.raises(zb.ZoneburnError) as e:
+            zb.tune_load(c2, p)
+        assert e.value.code == zb.EINVAL
+    assert zb.get_mapping(c2, net2, "mixed") == default
+    net2.close()
+    c2.close()
+
+
 @pytest.mark.parametrize("lanes", [1, 4])
 def test_variable_coefficient_bdf_robertson(zbm, lanes):
     zb, ctx = zbm

@@ -1,7 +1,7 @@
 """Host-side logic of the runtime built for the CPU alone, under AddressSanitizer and
 UndefinedBehaviorSanitizer (no GPU, no HIP): the context's slot rotation, the burn server's
-scheduling policy on a fake device, the series logarithm of the rate evaluation and the
-refinements of the step control."""
+scheduling policy on a fake device, the series logarithm of the rate evaluation, the
+refinements of the step control and the autotuner's JSON file."""
 import os
 import shutil
 import subprocess
@@ -45,3 +45,9 @@ def test_series_logarithm_is_within_1_2_ulp(tmp_path):
 def test_step_control_refinements_are_within_1_ulp(tmp_path):
     out = _build_and_run("stepmath_test.cpp", tmp_path)
     assert "stepmath ok" in out
+
+
+def test_tuning_file_reads_back_and_refuses_malformed_input(tmp_path):
+    out = _build_and_run("tunecache_test.cpp", tmp_path)
+    for part in ("round trip ok", "reordered ok", "refusals ok", "tunecache ok"):
+        assert part in out
