@@ -805,6 +805,11 @@ __device__ __forceinline__ void fd_jacobian(const Ctx &c, Zone<NVP, L, LT> &z,
 // registers.  The mixed path scales column j by the error weight w_j and the row by
 // 1 / max; the column scales in force are kept per zone for the solves, since a matrix
 // may be reused at later steps.
+// Kernels with one row a lane in a group narrower than the wave factor with the pivot order
+// of the zone's previous factorisation kept while it stays acceptable (lu_kept_order).
+template <int NVP, int L, class LT>
+constexpr bool kept_order() { return Zone<NVP, L, LT>::RPL == 1 && L >= 2 && L < 64; }
+
 template <int NVP, int L, class LT>
 __device__ __forceinline__ void form_M(const Ctx &c, Zone<NVP, L, LT> &z, double gamma)
 {
@@ -816,7 +821,9 @@ __device__ __forceinline__ void form_M(const Ctx &c, Zone<NVP, L, LT> &z, double
     constexpr bool MIXED = sizeof(LT) == 4;
     const double *wb = c.S + c.lay.wbuf;
     sfor<0, RPL>([&](auto S) {
-        int i = row_of<NVP, L>(c, S);
+        // one row a lane: the lane forms the row it held after the zone's last factorisation
+        // (the pivot order, identity at the zone's start); else its own rows
+        int i = kept_order<NVP, L, LT>() ? z.pivlane : row_of<NVP, L>(c, S);
         double rmax = 0.0;
         double mrow[NVP];
         if (i < N.nv) {
@@ -1175,6 +1182,52 @@ __device__ __forceinline__ void lu_factor(const Ctx &c, Zone<NVP, L, LT> &z)
     }
 }
 
+// The LU in the pivot order of the zone's previous factorisation, one row a lane: lane k
+// holds the k-th pivot row (form_M), so step k takes its pivot row from lane k by a
+// broadcast within the group (DPP), with no search and no data-dependent exchange.  Each
+// pivot must be at least PIV_KEEP times the largest candidate of its column (the rows not
+// yet eliminated), the threshold test of threshold partial pivoting; a step that fails it
+// makes the whole factorisation void (false), and the caller factors again with partial
+// pivoting.  In exact arithmetic the solutions are the same for every pivot order.
+constexpr float PIV_KEEP = 0.5f;
+
+template <int NVP, int L, class LT>
+__device__ __forceinline__ bool lu_kept_order(const Ctx &c, Zone<NVP, L, LT> &z)
+{
+    const int nv = own_copy(c.nv);
+    bool bad = false;
+    steps8<NVP>(nv, [&](auto K) {
+        constexpr int k = K;
+        const LT piv = bcast_k<L, k>(z.M[0][k]);
+        // lanes past nvp hold zero rows; the rows of lanes below k are eliminated
+        const LT a = c.gl >= k ? fabs(z.M[0][k]) : LT(0);
+        const LT gm = greduce<L>(a, OpMax());
+        bad = bad || !(fabs(piv) >= LT(PIV_KEEP) * gm);
+        const LT rinv = recip(piv);
+        if (c.gl == k) z.dinv[0] = rinv;
+        const bool act = c.gl > k;
+        const LT l = act ? z.M[0][k] * rinv : LT(0);
+        if (act) z.M[0][k] = l;
+        sfor<k + 1, NVP>([&](auto J) { z.M[0][J] = fma(-l, bcast_k<L, k>(z.M[0][J]), z.M[0][J]); });
+    });
+    return !gany<L>(bad);
+}
+
+// M = I - gamma J and its LU factors: in the kept pivot order where the kernel keeps one,
+// else (or when that order fails its threshold test) with partial pivoting from the natural
+// order, whose pivot order is then kept.
+template <int NVP, int L, class LT>
+__device__ __forceinline__ void factor_M(const Ctx &c, Zone<NVP, L, LT> &z, double gamma)
+{
+    form_M(c, z, gamma);
+    if constexpr (kept_order<NVP, L, LT>()) {
+        if (lu_kept_order(c, z)) return;
+        z.pivlane = c.gl;
+        form_M(c, z, gamma);
+    }
+    lu_factor(c, z);
+}
+
 // Solve M x = b: b by local row in, x by local component out (same slots).
 template <int NVP, int L, class LT>
 __device__ __forceinline__ void lu_solve(const Ctx &c, const Zone<NVP, L, LT> &z, double (&b)[Zone<NVP, L, LT>::RPL])
@@ -1358,6 +1411,7 @@ __device__ __forceinline__ int zone_start(const Ctx &c, Zone<NVP, L, LT> &z)
     z.nfe = 0;
     z.have_j = z.have_m = 0;
     z.nst_j = z.nst_m = 0;
+    z.pivlane = c.gl;   // the natural order: the first factorisation tests it
     z.gamma_m = 1.0;
     lds_fence();
     if (gany<L>(bad)) return ZB_ZONE_NONFINITE;
@@ -1549,8 +1603,7 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
         }
         z.nfe++;
         if (new_m) {
-            form_M(c, z, gamma);
-            lu_factor(c, z);
+            factor_M(c, z, gamma);
             z.nlu++;
             z.gamma_m = gamma;
             z.have_m = 1;
