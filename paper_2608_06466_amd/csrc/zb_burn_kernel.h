@@ -805,10 +805,11 @@ __device__ __forceinline__ void fd_jacobian(const Ctx &c, Zone<NVP, L, LT> &z,
 // registers.  The mixed path scales column j by the error weight w_j and the row by
 // 1 / max; the column scales in force are kept per zone for the solves, since a matrix
 // may be reused at later steps.
-// Kernels with one row a lane in a group narrower than the wave factor with the pivot order
-// of the zone's previous factorisation kept while it stays acceptable (lu_kept_order).
+// Kernels with one row a lane factor with the pivot order of the zone's previous
+// factorisation kept while it stays acceptable (lu_kept_order); the blocked matrix-core LU
+// does its own pivoting from the natural order.
 template <int NVP, int L, class LT>
-constexpr bool kept_order() { return Zone<NVP, L, LT>::RPL == 1 && L >= 2 && L < 64; }
+constexpr bool kept_order() { return Zone<NVP, L, LT>::RPL == 1 && L >= 2; }
 
 template <int NVP, int L, class LT>
 __device__ __forceinline__ void form_M(const Ctx &c, Zone<NVP, L, LT> &z, double gamma)
@@ -823,7 +824,7 @@ __device__ __forceinline__ void form_M(const Ctx &c, Zone<NVP, L, LT> &z, double
     sfor<0, RPL>([&](auto S) {
         // one row a lane: the lane forms the row it held after the zone's last factorisation
         // (the pivot order, identity at the zone's start); else its own rows
-        int i = kept_order<NVP, L, LT>() ? z.pivlane : row_of<NVP, L>(c, S);
+        int i = (kept_order<NVP, L, LT>() && !c.lu_blocked) ? z.pivlane : row_of<NVP, L>(c, S);
         double rmax = 0.0;
         double mrow[NVP];
         if (i < N.nv) {
@@ -1221,9 +1222,11 @@ __device__ __forceinline__ void factor_M(const Ctx &c, Zone<NVP, L, LT> &z, doub
 {
     form_M(c, z, gamma);
     if constexpr (kept_order<NVP, L, LT>()) {
-        if (lu_kept_order(c, z)) return;
-        z.pivlane = c.gl;
-        form_M(c, z, gamma);
+        if (!c.lu_blocked) {
+            if (lu_kept_order(c, z)) return;
+            z.pivlane = c.gl;
+            form_M(c, z, gamma);
+        }
     }
     lu_factor(c, z);
 }
