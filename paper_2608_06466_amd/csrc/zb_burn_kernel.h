@@ -56,16 +56,14 @@ __device__ __forceinline__ void lds_fence()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Pivot reciprocal.  FP64 divides (correctly rounded).  FP32 (the mixed-precision LU, an
-// approximate factorisation the Newton iteration absorbs) takes the hardware reciprocal and
-// one Newton step, within about an ulp, instead of the longer IEEE division sequence; a zero
-// pivot still yields a non-finite factor and so a failed Newton iteration.
-__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
-__device__ __forceinline__ float recip(float x)
-{
-    const float r = __builtin_amdgcn_rcpf(x);
-    return fmaf(fmaf(-x, r, 1.0f), r, r);
-}
+// Pivot reciprocal, off the IEEE division sequence, whose dependent chain each elimination
+// step waits on.  FP64: the hardware approximation refined by two Newton steps (within about
+// an ulp; on 2^20 zones of the 14-variable network every result came out bitwise as with the
+// division).  FP32 (the mixed-precision LU, an approximate factorisation the Newton
+// iteration absorbs): the hardware reciprocal alone, within an ulp.  A zero pivot still
+// yields a non-finite factor and so a failed Newton iteration.
+__device__ __forceinline__ double recip(double x) { return zbm::recip_from(x, __builtin_amdgcn_rcp(x)); }
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Load from global memory.  The network tables reach the kernel through generic
 // pointers, which compile to flat loads; those also count against the LDS wait counter,
@@ -405,6 +403,17 @@ __device__ __forceinline__ double lcoef(int q, int j)
     return v;
 }
 
+// l_0(q) = 1 / H_q (the divisions are done by the compiler)
+__device__ __forceinline__ double inv_harmonic(int q)
+{
+    double v = 1.0;
+    v = (q == 2) ? 1.0 / 1.5 : v;
+    v = (q == 3) ? 1.0 / (11.0 / 6.0) : v;
+    v = (q == 4) ? 1.0 / (25.0 / 12.0) : v;
+    v = (q == 5) ? 1.0 / (137.0 / 60.0) : v;
+    return v;
+}
+
 // H_q = 1 / l_0(q)
 __device__ __forceinline__ double harmonic(int q)
 {
@@ -613,7 +622,9 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
     if (N.thermal) {
         double T = ybuf[N.ns];
         lnT = zbm::log_series(T);
-        iT = 1.0 / T;
+        // the hardware reciprocal refined (zb_stepmath.h): on 2^20 zones of the 14-variable
+        // network the results came out bitwise as with the division, at fewer instructions
+        iT = zbm::recip_from(T, __builtin_amdgcn_rcp(T));
     }
     double sT = 0.0, sTT = 0.0;
     // the next reaction's parameters are loaded while the current one is processed
@@ -842,7 +853,7 @@ __device__ __forceinline__ void form_M(const Ctx &c, Zone<NVP, L, LT> &z, double
             rmax = 1.0;
         }
         if (MIXED) {
-            double sc = rmax > 0.0 ? 1.0 / rmax : 1.0;
+            double sc = rmax > 0.0 ? zbm::recip_from(rmax, __builtin_amdgcn_rcp(rmax)) : 1.0;
             z.rs[S] = (LT)sc;
             sfor<0, NVP>([&](auto J) { z.M[S][J] = (LT)(mrow[J] * sc); });
         } else {
@@ -1187,9 +1198,10 @@ __device__ __forceinline__ void lu_factor(const Ctx &c, Zone<NVP, L, LT> &z)
 // holds the k-th pivot row (form_M), so step k takes its pivot row from lane k by a
 // broadcast within the group (DPP), with no search and no data-dependent exchange.  Each
 // pivot must be at least PIV_KEEP times the largest candidate of its column (the rows not
-// yet eliminated), the threshold test of threshold partial pivoting; a step that fails it
-// makes the whole factorisation void (false), and the caller factors again with partial
-// pivoting.  In exact arithmetic the solutions are the same for every pivot order.
+// yet eliminated), the threshold test of threshold partial pivoting, checked lane by lane
+// and reduced once at the end; a step that fails it makes the whole factorisation void
+// (false), and the caller factors again with partial pivoting.  In exact arithmetic the
+// solutions are the same for every pivot order.
 constexpr float PIV_KEEP = 0.5f;
 
 template <int NVP, int L, class LT>
@@ -1200,10 +1212,9 @@ __device__ __forceinline__ bool lu_kept_order(const Ctx &c, Zone<NVP, L, LT> &z)
     steps8<NVP>(nv, [&](auto K) {
         constexpr int k = K;
         const LT piv = bcast_k<L, k>(z.M[0][k]);
-        // lanes past nvp hold zero rows; the rows of lanes below k are eliminated
-        const LT a = c.gl >= k ? fabs(z.M[0][k]) : LT(0);
-        const LT gm = greduce<L>(a, OpMax());
-        bad = bad || !(fabs(piv) >= LT(PIV_KEEP) * gm);
+        // each candidate against the pivot in its own lane, so no reduction per step: the
+        // rows of lanes below k are eliminated, lanes past nvp hold zero rows (a NaN fails)
+        if (c.gl > k) bad = bad || !(fabs(z.M[0][k]) <= fabs(piv) * LT(1.0f / PIV_KEEP));
         const LT rinv = recip(piv);
         if (c.gl == k) z.dinv[0] = rinv;
         const bool act = c.gl > k;
@@ -1328,7 +1339,7 @@ __device__ __forceinline__ void set_weights(const Ctx &c, Zone<NVP, L, LT> &z)
     for (int s = 0; s < RPL; ++s) {
         int i = row_of<NVP, L>(c, s);
         double w = z.atol + z.rtol * fabs(z.Z[0][s]);
-        z.iw[s] = (i < c.nv) ? 1.0 / w : 0.0;
+        z.iw[s] = (i < c.nv) ? zbm::recip_from(w, __builtin_amdgcn_rcp(w)) : 0.0;
         if (i < NVP) wb[i] = (i < c.nv) ? w : 1.0;
     }
 }
@@ -1576,7 +1587,7 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
     if constexpr (VC) {
         vc_coefficients(c, z.q, h, l0, ediv);
     } else {
-        l0 = 1.0 / harmonic(z.q);
+        l0 = inv_harmonic(z.q);
         ediv = (double)(z.q + 1);
     }
     const double gamma = h * l0;

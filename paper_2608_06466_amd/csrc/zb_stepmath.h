@@ -1,5 +1,6 @@
 // Double-precision reciprocal, square root and k-th root from approximate starting values,
-// for the step control of the burn kernels (WRMS norms and step-size factors).  The device
+// for the step control of the burn kernels (WRMS norms and step-size factors), and the
+// reciprocal also for the pivots, 1/T of the rates and the error weights.  The device
 // code starts from the hardware approximations (v_rcp_f64, v_sqrt_f64: about 2^-23
 // relative; the FP32 log2 and exp2 for the root) and refines them with Newton steps to
 // about 1 ulp, so that step sizes and accept/reject decisions agree with the exact formulas
