@@ -152,38 +152,23 @@ extern "C" zb_err zb_network_create(zb_context *ctx, const zb_network_desc *d, z
         rct[r] = make_int4(a, b, c, e);
         par[r] = make_double4(d->lnA[r], d->n_exp[r], d->E[r], q);
     }
-    // per-species involvement lists (net stoichiometry != 0) and reactant lists
+    // per-species involvement lists (net stoichiometry != 0)
     std::vector<std::vector<int2>> inv(ns);
-    std::vector<std::vector<int4>> rea(ns);
     for (int r = 0; r < nr; ++r) {
         const int4 x = rct[r];
-        unsigned long long qb;
-        memcpy(&qb, &par[r].w, sizeof qb);
         for (int i = 0; i < ns; ++i) {
             int nu = (x.z == i) + (x.w == i) - (x.x == i) - (x.y == i);
             if (nu != 0) inv[i].push_back(make_int2(r | (int)((unsigned)nu << 16), x.x | ((x.y + 1) << 8)));
-            int fl = (x.x == i ? 1 : 0) | (x.y == i ? 2 : 0);
-            if (fl) rea[i].push_back(make_int4(r | (fl << 16), 0, (int)(qb & 0xffffffffu), (int)(qb >> 32)));
         }
     }
-    int inv_len = 2, rea_len = 2;
-    for (int i = 0; i < ns; ++i) {
-        inv_len = std::max<int>(inv_len, (int)inv[i].size());
-        rea_len = std::max<int>(rea_len, (int)rea[i].size());
-    }
+    int inv_len = 2;
+    for (int i = 0; i < ns; ++i) inv_len = std::max<int>(inv_len, (int)inv[i].size());
     inv_len += inv_len & 1;   // even: the kernels take two entries per iteration
-    rea_len += rea_len & 1;
     std::vector<int2> invf((size_t)ns * inv_len, make_int2(0, 0));   // nu = 0 pads a row
-    std::vector<int4> reaf((size_t)ns * rea_len, make_int4(-1, 0, 0, 0));
-    for (int i = 0; i < ns; ++i) {
-        std::copy(inv[i].begin(), inv[i].end(), invf.begin() + (size_t)i * inv_len);
-        std::copy(rea[i].begin(), rea[i].end(), reaf.begin() + (size_t)i * rea_len);
-    }
+    for (int i = 0; i < ns; ++i) std::copy(inv[i].begin(), inv[i].end(), invf.begin() + (size_t)i * inv_len);
     size_t o_rct = 0, o_par = o_rct + sizeof(int4) * rct.size();
     size_t o_inv = o_par + sizeof(double4) * par.size();
-    size_t o_rea = o_inv + sizeof(int2) * invf.size();
-    o_rea = (o_rea + 15) & ~(size_t)15;
-    size_t bytes = o_rea + sizeof(int4) * reaf.size();
+    size_t bytes = o_inv + sizeof(int2) * invf.size();
     zb_network *n = new (std::nothrow) zb_network();
     if (!n) return fail(ZB_ENOMEM, "host allocation failed");
     DeviceGuard g(ctx->device);
@@ -196,7 +181,6 @@ extern "C" zb_err zb_network_create(zb_context *ctx, const zb_network_desc *d, z
     memcpy(host.data() + o_rct, rct.data(), sizeof(int4) * rct.size());
     memcpy(host.data() + o_par, par.data(), sizeof(double4) * par.size());
     memcpy(host.data() + o_inv, invf.data(), sizeof(int2) * invf.size());
-    memcpy(host.data() + o_rea, reaf.data(), sizeof(int4) * reaf.size());
     if (hipMemcpy(dm, host.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(dm);
         delete n;
@@ -209,11 +193,9 @@ extern "C" zb_err zb_network_create(zb_context *ctx, const zb_network_desc *d, z
     n->dn.thermal = th;
     n->dn.nr = nr;
     n->dn.inv_len = inv_len;
-    n->dn.rea_len = rea_len;
     n->dn.rct = (const int4 *)(dm + o_rct);
     n->dn.par = (const double4 *)(dm + o_par);
     n->dn.inv = (const int2 *)(dm + o_inv);
-    n->dn.rea = (const int4 *)(dm + o_rea);
     *out = n;
     return ZB_OK;
 }

@@ -18,17 +18,13 @@ constexpr int RMAX = 4096;   // largest number of reactions
 //              an arithmetic shift), .y = a_r | (b_r + 1) << 8 (the reactant columns
 //              the row's Jacobian entries go to, so no second lookup is needed);
 //              entries with nu = 0 (.x = 0) pad the row.
-//  rea[j][e], for every reaction with species j as a reactant: .x = r | flags << 16
-//              (flag 1: j is the first reactant, 2: the second), .zw = the bits of
-//              q_r; .x = -1 pads the row.
-//  Row lengths inv_len, rea_len are even (the kernels read two entries at a time).
+//  The row length inv_len is even (the kernels read two entries at a time).
 struct DevNet {
     int ns, nv, thermal, nr;
-    int inv_len, rea_len;
+    int inv_len;
     const int4 *rct;
     const double4 *par;
     const int2 *inv;
-    const int4 *rea;
 };
 
 // One run of zones that share a network and tolerances.
