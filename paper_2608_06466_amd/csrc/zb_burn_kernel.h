@@ -600,10 +600,21 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
             if (use_pre && P < n2) pre[P] = gload(l0 + P);
         });
     }
+    // one row a lane: T from its lane through the LDS crossbar, so that its logarithm and
+    // reciprocal overlap the stores below instead of waiting for them
+    double Tg = 0.0;
+    if constexpr (RPL == 1) Tg = gather(yv[0], (int)(threadIdx.x & (64 - L)) + N.ns);
 #pragma unroll
     for (int s = 0; s < RPL; ++s) {
         int i = row_of<NVP, L>(c, s);
         if (i < N.nv) ybuf[i] = yv[s];
+    }
+    double lnT = 0.0, iT = 0.0;
+    if constexpr (RPL == 1) {
+        if (N.thermal) {
+            lnT = zbm::log_series(Tg);
+            iT = zbm::recip_from(Tg, __builtin_amdgcn_rcp(Tg));
+        }
     }
     constexpr int JS = NVP + 1;   // Jacobian row stride in LDS
     const int nr = N.nr;
@@ -621,8 +632,7 @@ __device__ __forceinline__ void eval(const Ctx &c, Zone<NVP, L, LT> &z, const do
     }
     lds_fence();
 
-    double lnT = 0.0, iT = 0.0;
-    if (N.thermal) {
+    if (RPL > 1 && N.thermal) {
         double T = ybuf[N.ns];
         lnT = zbm::log_series(T);
         // the hardware reciprocal refined (zb_stepmath.h): on 2^20 zones of the 14-variable
