@@ -64,7 +64,8 @@ def transcendentals(nr, thermal, stats):
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "burn_kernel_14x16_nv14_2p20zones_hbm_traffic.md")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2608_06466_amd", "csrc", f)
-                  for f in ("zb_burn_kernel.h", "zb_internal.h", "zb_k14.hip")] + [
+                  for f in ("zb_burn_kernel.h", "zb_internal.h", "zb_log.h", "zb_stepmath.h",
+                            "zb_k14.hip")] + [
                   os.path.join(ROOT, "paper_2608_06466_amd", "build.py")]   # the compile flags
 
 
