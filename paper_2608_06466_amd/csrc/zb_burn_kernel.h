@@ -2032,12 +2032,16 @@ __device__ __forceinline__ void load_segment(Ctx &c, const BurnArgs &A, int seg,
 // SIMD; bounding them to two waves costs a few spilled registers and is ~20 %
 // faster (the LU and solve chains are latency-bound).  The smaller kernels are
 // left to the compiler (a bound there only adds spills).
-template <int NVP, int L, int JP>
+template <int NVP, int L, int JP, class LT>
 constexpr int min_waves_per_eu()
 {
     // the reuse kernels keep the factors live across steps: bounded to two waves too
     // the 8-row kernel fits three waves with a Jacobian every step
     if (NVP == 8 && L == 8 && (JP == METHOD_BDF || JP == METHOD_BDF_VC)) return 3;
+    // the mixed 14-row kernel with a Jacobian every step: three waves, at 168 VGPRs with
+    // 156 bytes a lane spilled, ran 1.1 % faster than two (the FP64 one 15 % slower: more
+    // spills; the same kernel without its list prefetch spilled less and ran 5 % slower)
+    if (NVP == 14 && L == 16 && JP == METHOD_BDF && sizeof(LT) == 4) return 3;
     // RKC keeps no matrix: four waves fit (the compiler would take two registers more)
     if (JP == METHOD_RKC) return 4;
     return ((NVP >= 48 && L == 64) || (method_jac(JP) == 1 && L >= 16)) ? 2 : 1;
@@ -2045,7 +2049,7 @@ constexpr int min_waves_per_eu()
 
 template <int NVP, int L, class LT, int JP>
 __global__ __launch_bounds__(64)
-__attribute__((amdgpu_waves_per_eu(min_waves_per_eu<NVP, L, JP>())))
+__attribute__((amdgpu_waves_per_eu(min_waves_per_eu<NVP, L, JP, LT>())))
 void burn_kernel(BurnArgs A)
 {
     extern __shared__ double smem[];
