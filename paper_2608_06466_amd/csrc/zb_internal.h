@@ -97,14 +97,16 @@ constexpr int VC_HIST = 0, VC_COUNT = QMAX, VC_L = QMAX + 1, VC_EDIV = 2 * QMAX 
 // eight zones share a CU (five with FP64 rows) at 150 reactions.
 __host__ __device__ constexpr bool jac_f32(int nvp, bool mixed) { return mixed && nvp >= 48; }
 
-// The trimmed layout of the FP64 whole-wave kernels (one row a lane), the one class whose
-// LDS, not its registers, bounds the zones a CU holds (five of a possible eight at 48 rows
-// and 150 reactions; six trimmed): the history copy has one slot per row instead of per
-// lane, there is no pivot-row buffer (pivot rows are read from registers), and the
-// per-reaction rate factors take no space when they are all 1.
+// The trimmed layout of the kernels with one row a lane in groups of 16 lanes or more (and
+// FP64 Jacobian rows): the history copy has one slot per row instead of per lane, there is
+// no pivot-row buffer (pivot rows are read from registers), and the per-reaction rate
+// factors take no space when they are all 1.  It is for the classes whose LDS, not their
+// registers, bounds the zones a CU holds: the FP64 48-row kernel (five of a possible eight
+// at 150 reactions, six trimmed), and the mixed 14-row one at three waves a SIMD (10
+// workgroups a CU, 11 trimmed: 7 % faster on the 2^20-zone headline, bitwise the same).
 __host__ __device__ constexpr bool lds_trim(int L, int rpl, bool jf32)
 {
-    return L == 64 && rpl == 1 && !jf32;
+    return L >= 16 && rpl == 1 && !jf32;
 }
 
 // L lanes per zone with rpl rows each.  rates: the per-reaction rate factors (the zone's rate
