@@ -27,8 +27,7 @@
  *           take the largest (ties keep q, then prefer q-1); change nothing when
  *           it is below 1.5, else eta = min(10, eta_p).  Order changes keep Z the
  *           interpolant of the last accepted values (Stirling coefficients).
- *  Failure  Newton failure: restore Z (by retracting the prediction, as VODE does), h *= 0.25.
- *           Error-test failure: restore Z likewise,
+ *  Failure  Newton failure: restore Z, h *= 0.25.  Error-test failure: restore Z,
  *           eta = max(0.1, 1 / ((6 E_q)^(1/(q+1)) + 1e-6)); from the third
  *           consecutive one, eta = 0.1 and the history restarts at order 1 from
  *           f at the accepted state.  Ten consecutive failures of either kind end
@@ -188,16 +187,6 @@ static void predict(int nv, int q, double *Z)
     for (int k = 0; k < q; k++)
         for (int j = q; j > k; j--)
             for (int i = 0; i < nv; i++) Z[(size_t)(j - 1) * nv + i] += Z[(size_t)j * nv + i];
-}
-
-/* The history before the prediction, after a failed attempt: VODE retracts the predicted
-   Nordsieck array (Brown, Byrne & Hindmarsh) instead of keeping a copy.  The exact inverse
-   of predict: its passes undone in reverse order, each pass's additions in reverse. */
-static void retract(int nv, int q, double *Z)
-{
-    for (int k = q - 1; k >= 0; k--)
-        for (int j = k + 1; j <= q; j++)
-            for (int i = 0; i < nv; i++) Z[(size_t)(j - 1) * nv + i] -= Z[(size_t)j * nv + i];
 }
 
 /* Iteration-matrix state of a zone.  Policy 0 (the default) evaluates J and factors
@@ -373,7 +362,7 @@ int orc_burn_zone_ex(const orc_net *net, double *row, const double *scale, const
     J.rtol = rtol;
     J.atol = atol;
     int nv = S.nv;
-    double Z[(ORC_QMAX + 2) * ORC_NVMAX];
+    double Z[(ORC_QMAX + 2) * ORC_NVMAX], Zs[(ORC_QMAX + 2) * ORC_NVMAX];
     double w[ORC_NVMAX], f0[ORC_NVMAX], f1[ORC_NVMAX], y1[ORC_NVMAX];
     double y[ORC_NVMAX], dy[ORC_NVMAX], dyprev[ORC_NVMAX];
     memset(st, 0, sizeof(*st));
@@ -417,6 +406,7 @@ int orc_burn_zone_ex(const orc_net *net, double *row, const double *scale, const
             last = 1;
         }
         for (int i = 0; i < nv; i++) w[i] = atol + rtol * fabs(Z[i]);
+        memcpy(Zs, Z, sizeof(double) * (size_t)(q + 1) * nv);
         predict(nv, q, Z);
         if (vc)
             coef_variable(q, h, hist, nh, &C);
@@ -424,7 +414,7 @@ int orc_burn_zone_ex(const orc_net *net, double *row, const double *scale, const
             coef_fixed(q, &C);
 
         if (newton(&S, &J, &C, h, Z, w, y, dy, st)) {
-            retract(nv, q, Z);
+            memcpy(Z, Zs, sizeof(double) * (size_t)(q + 1) * nv);
             st->ncf++;
             if (++ncf >= 10) { status = ORC_CONV; break; }
             rescale(nv, q, Z, 0.25);
@@ -441,16 +431,13 @@ int orc_burn_zone_ex(const orc_net *net, double *row, const double *scale, const
         double feas = 1.0;
         for (int i = 0; i < net->ns && i < nv; i++) {
             if (y[i] < -atol) {
-                /* y_i before the prediction: row 0 of the inverse Pascal matrix applied to
-                   the predicted history, sum_j (-1)^j Z_j, in order of j */
-                double old = Z[i];
-                for (int j = 1; j <= q; j++) old += (j & 1 ? -1.0 : 1.0) * Z[(size_t)j * nv + i];
+                double old = Zs[i];
                 double frac = (old + atol) / (old - y[i]);
                 feas = fmin(feas, frac);
             }
         }
         if (err > 1.0 || feas < 1.0) {
-            retract(nv, q, Z);
+            memcpy(Z, Zs, sizeof(double) * (size_t)(q + 1) * nv);
             st->netf++;
             if (++nef >= 10) { status = ORC_ERRTEST; break; }
             double eta = err > 1.0 ? fmax(0.1, 1.0 / (pow(6.0 * err, 1.0 / (q + 1)) + 1e-6)) : 1.0;
