@@ -471,7 +471,8 @@ template <int NVP, int L, class LT>
 struct Zone {
     static constexpr int RPL = (NVP + L - 1) / L;
     double Z[QMAX + 1][RPL];    // Nordsieck history, local rows (the copy taken before
-                                // each prediction is kept in LDS)
+                                // each prediction is kept in LDS, or in registers of the
+                                // attempt where hist_regs says so)
     double dyp[RPL];            // dy of the previous accepted step
     double iw[RPL];             // 1 / (atol + rtol |y|)
     double y[RPL], dy[RPL], f[RPL];
@@ -1548,7 +1549,7 @@ __device__ __forceinline__ void vc_coefficients(const Ctx &c, int q, double h, d
     }
 }
 
-template <bool VC, int NVP, int L, class LT>
+template <bool VC, bool HREGS, int NVP, int L, class LT>
 __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
 {
     constexpr int RPL = Zone<NVP, L, LT>::RPL;
@@ -1563,7 +1564,26 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
         last = true;
     }
     set_weights(c, z);
-    save_history(c, z);
+    // the history before the prediction: in registers of the attempt or in LDS (hist_regs)
+    double Zs[HREGS ? QMAX + 1 : 1][RPL];
+    if constexpr (HREGS) {
+#pragma unroll
+        for (int j = 0; j <= QMAX; ++j)
+#pragma unroll
+            for (int s = 0; s < RPL; ++s) Zs[j][s] = z.Z[j][s];
+    } else {
+        save_history(c, z);
+    }
+    auto restore = [&]() {
+        if constexpr (HREGS) {
+#pragma unroll
+            for (int j = 0; j <= QMAX; ++j)
+#pragma unroll
+                for (int s = 0; s < RPL; ++s) z.Z[j][s] = Zs[j][s];
+        } else {
+            restore_history(c, z);
+        }
+    };
     // prediction: Pascal triangle, over every order (the columns past q are zero, so the
     // extra additions add zeros: no branch on q)
 #pragma unroll
@@ -1619,7 +1639,7 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
     }
 
     if (!conv) {
-        restore_history(c, z);
+        restore();
         z.ncf++;
         if (++z.ncfc >= 10) return ZB_ZONE_CONV;
         rescale(z, 0.25);
@@ -1639,14 +1659,15 @@ __device__ __forceinline__ int zone_attempt(const Ctx &c, Zone<NVP, L, LT> &z)
         for (int s = 0; s < RPL; ++s) {
             const int i = row_of<NVP, L>(c, s);
             if (i < c.ns && z.y[s] < -z.atol) {
-                const double old = zs[zs_slot<NVP, L, RPL, LT>(c.gl, 0, s)];   // Z_0 before the prediction
+                // Z_0 before the prediction
+                const double old = HREGS ? Zs[0][s] : zs[zs_slot<NVP, L, RPL, LT>(c.gl, 0, s)];
                 feas = fmin(feas, (old + z.atol) / (old - z.y[s]));
             }
         }
         feas = greduce<L>(feas, OpMin());
     }
     if (err > 1.0 || feas < 1.0) {
-        restore_history(c, z);
+        restore();
         z.netf++;
         if (++z.nefc >= 10) return ZB_ZONE_ERRTEST;
         double eta = err > 1.0 ? fmax(0.1, step_factor(6.0 * err, z.q + 1)) : 1.0;
@@ -2012,7 +2033,7 @@ __device__ __forceinline__ T uniform(T v)
 
 // Segment data for the wave (the wave works on one segment at a time, so it is uniform).
 __device__ __forceinline__ void load_segment(Ctx &c, const BurnArgs &A, int seg, int nvp, int L,
-                                             int rpl, bool vc, bool jf32)
+                                             int rpl, bool vc, bool jf32, bool hregs)
 {
     // seg is wave-uniform: scalar loads from the kernel-argument segment
     const BurnArgs *pa = (const BurnArgs *)__builtin_amdgcn_kernarg_segment_ptr();
@@ -2021,7 +2042,7 @@ __device__ __forceinline__ void load_segment(Ctx &c, const BurnArgs &A, int seg,
     c.ns = uniform(S.net.ns);
     c.nv = uniform(S.net.nv);
     c.rates = pa->rates_lds != 0;
-    c.lay = lds_layout(nvp, L, rpl, A.max_nr, vc, jf32, c.rates);
+    c.lay = lds_layout(nvp, L, rpl, A.max_nr, vc, jf32, c.rates, hregs);
 }
 
 // Persistent kernel.  Each wave works through the segments in order; within a
@@ -2064,7 +2085,8 @@ void burn_kernel(BurnArgs A)
     c.lu_blocked = method_blocked_lu(JP);   // a constant: each
                          // method is its own kernel (the reuse keeps the
                          // factors live across steps, which costs registers)
-    load_segment(c, A, seg, NVP, L, RPL, method_vc(JP), jac_f32(NVP, sizeof(LT) == 4));
+    load_segment(c, A, seg, NVP, L, RPL, method_vc(JP), jac_f32(NVP, sizeof(LT) == 4),
+                 hist_regs(NVP, L, sizeof(LT) == 4, JP));
     c.S = smem + g * c.lay.total;
     // zones of a segment: its own, or in the FP64 run of the fallback those on its list
     auto seg_zones = [&](int sg) -> int64_t {
@@ -2100,7 +2122,8 @@ void burn_kernel(BurnArgs A)
         }
         if (__ballot(!dry) == 0) {
             if (++seg >= A.nseg) break;
-            load_segment(c, A, seg, NVP, L, RPL, method_vc(JP), jac_f32(NVP, sizeof(LT) == 4));
+            load_segment(c, A, seg, NVP, L, RPL, method_vc(JP), jac_f32(NVP, sizeof(LT) == 4),
+                 hist_regs(NVP, L, sizeof(LT) == 4, JP));
             c.S = smem + g * c.lay.total;
             zones = uniform(seg_zones(__builtin_amdgcn_readfirstlane(seg)));
             need = true;
@@ -2108,7 +2131,8 @@ void burn_kernel(BurnArgs A)
             continue;
         }
         if (!need) {
-            int st = (JP == METHOD_RKC) ? zone_attempt_rkc(c, z) : zone_attempt<method_vc(JP)>(c, z);
+            int st = (JP == METHOD_RKC) ? zone_attempt_rkc(c, z)
+                                        : zone_attempt<method_vc(JP), hist_regs(NVP, L, sizeof(LT) == 4, JP)>(c, z);
             if (st != RUNNING) {
                 if (st != ZB_ZONE_OK && A.retry && z.tries == 0) {
                     // Zone-by-zone retry with the retry tolerances, from the zone's input

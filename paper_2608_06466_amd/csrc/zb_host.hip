@@ -229,7 +229,8 @@ static size_t launch_lds(const KernelInfo *k, int max_nr, bool rates = true)
     const int G = 64 / k->lanes;
     const int rpl = (k->nvp + k->lanes - 1) / k->lanes;
     const LdsLayout lay = lds_layout(k->nvp, k->lanes, rpl, max_nr, method_vc(k->jac),
-                                     jac_f32(k->nvp, k->mixed != 0), rates);
+                                     jac_f32(k->nvp, k->mixed != 0), rates,
+                                     hist_regs(k->nvp, k->lanes, k->mixed != 0, k->jac));
     return (size_t)G * lay.total * sizeof(double);
 }
 

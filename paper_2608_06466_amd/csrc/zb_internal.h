@@ -81,6 +81,17 @@ __host__ __device__ constexpr bool method_blocked_lu(int m)
     return m == METHOD_BDF_BLU || m == METHOD_BDF_VC_BLU;
 }
 
+// The history copy of a step attempt (the Nordsieck array before the prediction, restored
+// after a failed attempt) is held in registers in the mixed 14-row kernel with a Jacobian
+// every step, whose LDS bounds the workgroups a CU holds (12 without the copy's 84 doubles a
+// zone, 11 with them: 5 % faster on the 2^20-zone headline, bitwise the same).  Elsewhere
+// registers bound them, and the copy stays in LDS (in registers it made the batched FP64
+// burn 7 % slower, the 48-row kernel spilling more).
+__host__ __device__ constexpr bool hist_regs(int nvp, int L, bool mixed, int method)
+{
+    return nvp == 14 && L == 16 && mixed && method == METHOD_BDF;
+}
+
 // Per-group LDS layout (in doubles).  Everything a zone group exchanges lives here.
 struct LdsLayout {
     int cnt, zs, ybuf, wbuf, prow, ks, rx, jbuf, vc, total;
@@ -113,13 +124,13 @@ __host__ __device__ constexpr bool lds_trim(int L, int rpl, bool jf32)
 // scales, or a network's constant rates when it has no temperature) are needed; without
 // rate scales and with a temperature variable they are all 1.
 __host__ __device__ inline LdsLayout lds_layout(int nvp, int L, int rpl, int nr, bool vc,
-                                                bool jf32, bool rates)
+                                                bool jf32, bool rates, bool hregs)
 {
     const bool trim = lds_trim(L, rpl, jf32);
     LdsLayout o;
     int p = 0;
     o.cnt = p;  p += 4;               // counters of a zone's first run while it is retried
-    o.zs = p;   p += (QMAX + 1) * (trim ? nvp : L * rpl);
+    o.zs = p;   p += hregs ? 0 : (QMAX + 1) * (trim ? nvp : L * rpl);
     o.ybuf = p; p += nvp;
     o.wbuf = p; p += nvp;
     o.prow = p; p += trim ? 0 : nvp;
