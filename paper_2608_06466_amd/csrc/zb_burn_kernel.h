@@ -2057,12 +2057,17 @@ template <int NVP, int L, int JP, class LT>
 constexpr int min_waves_per_eu()
 {
     // the reuse kernels keep the factors live across steps: bounded to two waves too
+    // (but for the mixed 14-row ones below)
     // the 8-row kernel fits three waves with a Jacobian every step
     if (NVP == 8 && L == 8 && (JP == METHOD_BDF || JP == METHOD_BDF_VC)) return 3;
     // the mixed 14-row kernel with a Jacobian every step: three waves, at 168 VGPRs with
     // 156 bytes a lane spilled, ran 1.1 % faster than two (the FP64 one 15 % slower: more
-    // spills; the same kernel without its list prefetch spilled less and ran 5 % slower)
-    if (NVP == 14 && L == 16 && JP == METHOD_BDF && sizeof(LT) == 4) return 3;
+    // spills; the same kernel without its list prefetch spilled less and ran 5 % slower).
+    // The mixed reuse kernels too (268 bytes spilled), with the history copy in registers:
+    // 11 % faster (fixed-coefficient form) and 2 % (variable-coefficient form)
+    if (NVP == 14 && L == 16 && sizeof(LT) == 4 &&
+        (JP == METHOD_BDF || JP == METHOD_BDF_REUSE || JP == METHOD_BDF_VC_REUSE))
+        return 3;
     // RKC keeps no matrix: four waves fit (the compiler would take two registers more)
     if (JP == METHOD_RKC) return 4;
     return ((NVP >= 48 && L == 64) || (method_jac(JP) == 1 && L >= 16)) ? 2 : 1;
