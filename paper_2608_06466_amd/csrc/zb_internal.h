@@ -83,15 +83,17 @@ __host__ __device__ constexpr bool method_blocked_lu(int m)
 
 // The history copy of a step attempt (the Nordsieck array before the prediction, restored
 // after a failed attempt) is held in registers in the mixed 14-row kernels that run three
-// waves a SIMD (a Jacobian every step, and the two reuse forms), whose LDS bounds the
+// waves a SIMD (a Jacobian every step, and the two reuse forms) and the mixed 22-row one
+// with a Jacobian every step (three waves as well: 14 % faster), whose LDS bounds the
 // workgroups a CU holds (12 without the copy's 84 doubles a zone, 11 with them: 5 % faster
 // on the 2^20-zone headline, bitwise the same).  Elsewhere registers bound them, and the
 // copy stays in LDS (in registers it made the batched FP64 burn 7 % slower, the 48-row
 // kernel spilling more).
 __host__ __device__ constexpr bool hist_regs(int nvp, int L, bool mixed, int method)
 {
-    return nvp == 14 && L == 16 && mixed &&
-           (method == METHOD_BDF || method == METHOD_BDF_REUSE || method == METHOD_BDF_VC_REUSE);
+    return (nvp == 14 && L == 16 && mixed &&
+            (method == METHOD_BDF || method == METHOD_BDF_REUSE || method == METHOD_BDF_VC_REUSE)) ||
+           (nvp == 22 && L == 32 && mixed && method == METHOD_BDF);
 }
 
 // Per-group LDS layout (in doubles).  Everything a zone group exchanges lives here.
